@@ -1,0 +1,204 @@
+/*
+ * wavedd: block-level non-overlapping domain decomposition for the 2D
+ * Helmholtz equation with impedance boundary and transmission conditions,
+ * subdomain problems solved by WaveHoltz, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. Rotem, "Efficient Domain Decomposition for the Helmholtz
+ * Equation on GPUs".
+ *   Problem       Sec. II eq. (1):  -Lap u - k^2 u = f,  d_n u - i k u = g,
+ *                 k = omega / c(x), time convention e^{-i omega t}.
+ *   Discretisation Sec. IV eq. (4): (A - i omega H - omega^2 M) u = b with a
+ *                 tensor-product GLL spectral-element basis of degree P on
+ *                 uniform axis-aligned quadrilaterals and GLL quadrature, so
+ *                 M and H are diagonal and A is a Kronecker sum.
+ *   DD            Sec. III: non-overlapping subdomains coupled by
+ *                 zeroth-order impedance conditions; dual variables updated
+ *                 by eq. (2) (sign read so that the fixed point is the global
+ *                 discrete solution: g_r <- -g_l - 2 i k u_l).
+ *   Subdomain solve Sec. V eqs. (6)-(7) and Algorithm 1: WaveHoltz with the
+ *                 modified leapfrog scheme, all subdomains in one launch.
+ *   Outer         Sec. III (last paragraph): the sweep is affine in the
+ *                 interface data, G' = T G + h; (I - T) G = h is solved by
+ *                 restarted GMRES in FP64 (or plain fixed-point iteration).
+ *
+ * Conventions
+ *   Global nodes (i, j), i along x, j along y; flat index j * Nx + i with
+ *   Nx = nx*P + 1, Ny = ny*P + 1, N = Nx * Ny.
+ *   Boundary traces (g on the outer boundary) are arrays of length
+ *   2*Ny + 2*Nx: left side (x = x0, by increasing y), right side (x = x1),
+ *   bottom side (y = y0, by increasing x), top side (y = y1).  Each side
+ *   carries its own value at a corner.
+ *   Subdomain l = b * sx + a covers element columns [a*mx, (a+1)*mx) and
+ *   rows [b*my, (b+1)*my), mx = nx/sx, my = ny/sy; its local nodes (il, jl)
+ *   are stored row-major, nloc = (mx*P+1) * (my*P+1) per subdomain.
+ *   Interface arrays ("g layout", used by dd_sweep): for each subdomain l,
+ *   the sides left, right, bottom, top, each ordered by increasing
+ *   coordinate, of lengths nyl, nyl, nxl, nxl (nxl = mx*P+1, nyl = my*P+1).
+ *
+ * Errors: every entry point returns 0 on success or a negative DD_E* code;
+ * dd_last_error() returns a thread-local message for the last failure.  All
+ * argument validation happens before any device work.
+ * Threading: a handle is used by one host thread at a time and issues its
+ * work on one HIP stream; separate handles are independent.
+ * Memory: the library owns all device memory it allocates; host arrays
+ * passed in are read or written only during the call.
+ */
+#ifndef WAVEDD_H
+#define WAVEDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_OK 0
+#define DD_EINVAL (-1)     /* bad shape or value, detected before device work */
+#define DD_ENOMEM (-2)     /* device allocation failed */
+#define DD_EHIP (-3)       /* HIP runtime error (message in dd_last_error) */
+#define DD_ENAN (-4)       /* non-finite input or iterate */
+#define DD_ENOTCONV (-5)   /* max_iter reached: outputs and stats ARE written */
+#define DD_ENODEV (-6)     /* no usable gfx950 device */
+
+#define DD_FP64 0          /* subdomain sweep in double precision */
+#define DD_FP32 1          /* subdomain sweep in single precision, outer FP64 */
+
+#define DD_LAYOUT_AUTO 0   /* pick by measurement (autotuner) */
+#define DD_LAYOUT_NODE 1   /* one DOF per thread, state in registers + LDS */
+#define DD_LAYOUT_PATCH 2  /* one element patch (P*P DOFs) per thread */
+
+#define DD_OUTER_GMRES 0
+#define DD_OUTER_FIXED 1
+
+typedef struct dd_handle dd_handle;
+
+/* nx x ny uniform quadrilateral elements on [x0,x1] x [y0,y1]. */
+typedef struct {
+    int nx, ny;
+    double x0, x1, y0, y1;
+} dd_mesh;
+
+/* sx x sy grid of equal element blocks; sx | nx and sy | ny. */
+typedef struct {
+    int sx, sy;
+} dd_partition;
+
+typedef struct {
+    int precision;   /* DD_FP64 | DD_FP32 */
+    int layout;      /* DD_LAYOUT_* */
+    double tau_in;   /* WaveHoltz stop: ||u_new-u|| <= tau_in ||u_new||; <= 0: fixed count */
+    int max_wh;      /* WaveHoltz iteration cap (the fixed count when tau_in <= 0) */
+    int outer;       /* DD_OUTER_GMRES | DD_OUTER_FIXED */
+    int restart;     /* GMRES restart length m */
+    int nt_override; /* > 0: use this many time steps per period in every subdomain */
+    double cfl;      /* safety factor s in (0, 1] of the time-step rule */
+} dd_options;
+
+typedef struct {
+    int outer_iters;            /* outer iterations (= sweeps with sources off) */
+    int sweeps;                 /* all sweep launches of the solve */
+    double rel_residual;        /* outer residual estimate ||h-(I-T)G||/||h|| at exit */
+    double true_rel_residual;   /* same, recomputed with one extra sweep at exit */
+    int64_t wh_iters_total;     /* WaveHoltz iterations summed over subdomains and sweeps */
+    int wh_iters_max;           /* largest per-subdomain count in any sweep */
+    int nt_min, nt_max;         /* time steps per period over subdomains */
+    double dof_updates;         /* sum over sweeps/subdomains of nloc*(N_t-1)*iterations */
+    double sweep_seconds;       /* device time inside sweep launches */
+    double seconds;             /* wall time of the call */
+} dd_stats;
+
+/* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
+ * no N_t override, cfl 0.9. */
+int dd_default_options(dd_options* opt);
+
+/* Set up a problem (Sec. II-IV): mesh, degree P in [1, 4], wavespeed c > 0
+ * sampled at the N global GLL nodes (host array, copied), omega > 0,
+ * partition, options (NULL = defaults).  Computes GLL tables, the lumped M
+ * and H of every subdomain (all four sides of a subdomain carry impedance
+ * terms), the leapfrog coefficients alpha, beta and sigma, the filter tables
+ * and N_t per subdomain, and uploads them.  *out receives a new handle. */
+int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wavespeed,
+             double omega, const dd_partition* part, const dd_options* opt);
+
+void dd_destroy(dd_handle* h);
+
+/* Thread-local description of the last error. */
+const char* dd_last_error(void);
+
+/* Sizes: global nodes N, nodes per subdomain, number of subdomains,
+ * interface-array length, outer boundary trace length (2*Ny + 2*Nx). */
+int dd_sizes(const dd_handle* h, int64_t* n_global, int64_t* n_local, int64_t* n_sub,
+             int64_t* n_iface, int64_t* n_trace);
+
+/* Global GLL node coordinates (x[N], y[N]; caller-owned). */
+int dd_node_coords(const dd_handle* h, double* x, double* y);
+
+/* Per-subdomain N_t (n_sub ints, caller-owned). */
+int dd_time_steps(const dd_handle* h, int* nt);
+
+/* Solve (Sec. III outer iteration over Algorithm 1 sweeps).  f: nodal
+ * source at the N global nodes (f_im may be NULL); g: outer boundary trace
+ * (NULL = 0; either part may be NULL).  tol: relative outer residual;
+ * max_iter: outer iteration cap.  u: caller-owned N-arrays, the glued
+ * solution (average of subdomain copies).  st may be NULL.  Returns
+ * DD_ENOTCONV (with outputs written) when max_iter is reached. */
+int dd_solve(dd_handle* h, const double* f_re, const double* f_im, const double* g_re,
+             const double* g_im, double tol, int max_iter, double* u_re, double* u_im,
+             dd_stats* st);
+
+/* Same, with device pointers (hipMalloc'd, FP64) and an explicit stream
+ * (hipStream_t passed as void*; NULL = the handle's stream).  g may be NULL.
+ * Also writes the stacked subdomain copies to u_sub (n_sub*n_local complex,
+ * interleaved re/im) when non-NULL. */
+int dd_solve_device(dd_handle* h, void* stream, const double* d_f_re, const double* d_f_im,
+                    const double* d_g_re, const double* d_g_im, double tol, int max_iter,
+                    double* d_u_re, double* d_u_im, double* d_u_sub, dd_stats* st);
+
+/* One DD cycle (Algorithm 1) on every subdomain in one launch: b from
+ * src * (f, phi) + sum_sides W_side g_in, WaveHoltz from u = 0, then the
+ * interface update into g_out (physical slots set to 0).  Host arrays in
+ * the g layout (n_iface each); f as in dd_solve (NULL = 0); u_sub: stacked
+ * subdomain solutions (n_sub*n_local each, may be NULL); wh_iters: per
+ * subdomain WaveHoltz counts (may be NULL). */
+int dd_sweep(dd_handle* h, const double* g_re, const double* g_im, const double* f_re,
+             const double* f_im, double src, double* g_out_re, double* g_out_im,
+             double* u_re, double* u_im, int* wh_iters);
+
+/* Apply the subdomain stiffness A_l (Sec. IV, eq. (4)) to stacked nodal
+ * vectors p (n_sub*n_local) with the sweep kernel's own device routine:
+ * q = A p.  Host arrays. */
+int dd_apply_stiffness(dd_handle* h, const double* p, double* q);
+
+/* Relative residual ||b - S u||_2 / ||b||_2 of the global system eq. (4) in
+ * FP64 for a glued nodal u (host arrays; f_im, g may be NULL). */
+int dd_residual(dd_handle* h, const double* u_re, const double* u_im, const double* f_re,
+                const double* f_im, const double* g_re, const double* g_im, double* rel);
+
+/* Whole-domain operator y = S x in FP64 on device arrays (x, y: N complex,
+ * interleaved re/im): the normaliser of the paper's DD-time/operator-time
+ * ratio (Sec. VII-A). */
+int dd_apply_operator_device(dd_handle* h, void* stream, const double* d_x, double* d_y);
+
+/* Outer state for warm restart / checkpointing: the interface vector G
+ * (n_iface complex, interleaved re/im, host). */
+int dd_get_state(const dd_handle* h, double* G);
+int dd_set_state(dd_handle* h, const double* G);
+
+/* Time sweep launches with events on the handle's stream (the paper's
+ * DD-cycle timing, Sec. VII-A): the input is the current outer state G (left
+ * by the last solve or set by dd_set_state), sources off.  fixed_iters > 0
+ * runs exactly that many WaveHoltz iterations per subdomain (the paper uses
+ * five); 0 keeps the handle's tolerance.  Returns the average milliseconds
+ * per launch over `reps` launches after one warm-up, and the DOF-updates of
+ * one launch (sum over subdomains of nloc*(N_t-1)*iterations; may be NULL). */
+int dd_time_sweep(dd_handle* h, int reps, int fixed_iters, double* ms, double* dof_updates);
+
+/* Current layout (DD_LAYOUT_NODE or DD_LAYOUT_PATCH) and threads/workgroup. */
+int dd_layout(const dd_handle* h, int* layout, int* wg_threads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVEDD_H */

@@ -1,0 +1,896 @@
+// Sweep kernels: one DD cycle (Algorithm 1: assemble b, WaveHoltz, interface
+// update) for every subdomain, one workgroup per subdomain, all subdomains
+// in one launch.
+//
+// The stiffness is the assembled GLL-quadrature form A = Kx (x) Wy + Wx (x) Ky
+// (Sec. IV: GLL quadrature at the nodes), applied per unique DOF as two 1D
+// banded sums (no element redundancy, no atomics, deterministic order):
+//   (A p)_{ij} = (2/hx) Wy_j X_ij + (2/hy) Wx_i Y_ij,
+//   X_ij = sum_k Khat_x[i,k] p_kj,   Y_ij = sum_k Khat_y[j,k] p_ik,
+// Khat the assembled reference 1D stiffness (element blocks D^T W D).  The
+// weights are folded with beta into per-node coefficients betaX, betaY.
+//
+// Two layouts:
+//  * PATCH: thread t = ey*mx + ex owns the P*P nodes (ex*P+a, ey*P+b),
+//    a,b < P, of element (ex, ey), in registers; the subdomain's right
+//    column and top row of nodes (mx*P + my*P + 1 of them) are an extra
+//    one-node "edge" slot on the first threads.  Only element-boundary values
+//    cross threads: each step a thread publishes its a=0 column and b=0 row,
+//    reads its right neighbour's column and top neighbour's row, and exchanges
+//    partial sums for the shared vertex lines (two workgroup barriers per
+//    step).  Interior slots finish between the two barriers.
+//  * NODE: one thread per node (<= 1024 nodes); p double-buffered in LDS
+//    with zero padding, so the (2P+1)-point 1D windows need no bounds
+//    checks (one barrier per step).
+// Both stage the per-step filter / forcing tables of the subdomain in LDS
+// (broadcast reads) when the subdomain starts.
+#include "wavedd_internal.h"
+
+namespace wdd {
+
+namespace {
+
+// Deterministic workgroup sum of two FP64 values (butterfly within each
+// wave, then a fixed-order sum over waves).  All threads must call it.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        s0 += red[2 * i];
+        s1 += red[2 * i + 1];
+    }
+    a = s0;
+    b = s1;
+    __syncthreads();
+}
+
+// b_j = src * F_j + sum over the subdomain sides through node (il, jl) of
+// W_side(j) * g_side(j)  (b of eq. (4) with the interface data as lambda).
+template <typename Real>
+__device__ __forceinline__ double2 assemble_b(const SweepArgs<Real>& A, const SubDesc& d, int il,
+                                              int jl) {
+    const int64_t node = d.node_off + (int64_t)jl * d.nxl + il;
+    double br = 0.0, bi = 0.0;
+    if (A.Fre) {
+        br = A.src * (double)A.Fre[node];
+        bi = A.src * (double)A.Fim[node];
+    }
+    const double* wx = A.w1d + d.w_off;
+    const double* wy = wx + d.nxl;
+    const int64_t o = d.if_off;
+    if (il == 0) {
+        const double2 g = A.g_in[o + jl];
+        br += wy[jl] * g.x;
+        bi += wy[jl] * g.y;
+    }
+    if (il == d.nxl - 1) {
+        const double2 g = A.g_in[o + d.nyl + jl];
+        br += wy[jl] * g.x;
+        bi += wy[jl] * g.y;
+    }
+    if (jl == 0) {
+        const double2 g = A.g_in[o + 2 * d.nyl + il];
+        br += wx[il] * g.x;
+        bi += wx[il] * g.y;
+    }
+    if (jl == d.nyl - 1) {
+        const double2 g = A.g_in[o + 2 * d.nyl + d.nxl + il];
+        br += wx[il] * g.x;
+        bi += wx[il] * g.y;
+    }
+    return make_double2(br, bi);
+}
+
+// Per-node state and coefficients of one owned node (edge and node slots).
+template <typename Real>
+struct Slot {
+    Real p, pd, vr, vi;         // p, pdot^{nu+1/2}, filter sums (Re, Im / omega)
+    Real al, bX, bY, bbr, bbi;  // alpha, betaX, betaY, beta*Re b, beta*Im b
+    int64_t node;               // index into the per-node arrays
+};
+
+template <typename Real>
+__device__ __forceinline__ void slot_zero(Slot<Real>& s) {
+    s.p = s.pd = s.vr = s.vi = Real(0);
+    s.al = s.bX = s.bY = s.bbr = s.bbi = Real(0);
+    s.node = 0;
+}
+
+template <typename Real>
+__device__ __forceinline__ void slot_load(Slot<Real>& s, const SweepArgs<Real>& A,
+                                          const SubDesc& d, int il, int jl) {
+    s.node = d.node_off + (int64_t)jl * d.nxl + il;
+    s.al = A.coef.alpha[s.node];
+    s.bX = A.coef.betaX[s.node];
+    s.bY = A.coef.betaY[s.node];
+    const double be = (double)A.coef.beta[s.node];
+    const double2 b = assemble_b(A, d, il, jl);
+    s.bbr = (Real)(be * b.x);
+    s.bbi = (Real)(be * b.y);
+}
+
+// Start of a WaveHoltz iteration (Algorithm 1): p = Re u,
+// pdot^{1/2} = Re{-i omega u e^{-i pi/N_t}}, v = kappa_0 p + (i/omega) kappa_{1/2} pdot.
+template <typename Real>
+__device__ __forceinline__ void slot_init(Slot<Real>& s, const SweepArgs<Real>& A,
+                                          const SubDesc& d, bool from_u, Real k0, Real kh0) {
+    if (from_u) {
+        const double2 u = A.u[s.node];
+        s.p = (Real)u.x;
+        s.pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
+    } else {
+        s.p = Real(0);
+        s.pd = Real(0);
+    }
+    s.vr = k0 * s.p;
+    s.vi = kh0 * s.pd;
+}
+
+// One leapfrog velocity update plus filter accumulation, given the
+// reference x/y stiffness sums X, Y at the node.
+template <typename Real>
+__device__ __forceinline__ void slot_step(Slot<Real>& s, Real X, Real Y, Real c, Real sn, Real k1,
+                                          Real k2) {
+    Real t = s.bbr * c;
+    t = fma(s.bbi, sn, t);
+    t = fma(-s.bX, X, t);
+    t = fma(-s.bY, Y, t);
+    s.pd = fma(s.al, s.pd, t);
+    s.vr = fma(k1, s.p, s.vr);
+    s.vi = fma(k2, s.pd, s.vi);
+}
+
+// End of a WaveHoltz iteration: u_new = (2/N_t) v (eq. (7)); accumulate
+// ||u_new - u_old||^2 and ||u_new||^2.
+template <typename Real>
+__device__ __forceinline__ void slot_finish(const Slot<Real>& s, const SweepArgs<Real>& A,
+                                            const SubDesc& d, bool has_old, double& dsum,
+                                            double& nsum) {
+    const double ur = d.two_over_nt * (double)s.vr;
+    const double ui = d.two_over_nt * (double)s.vi;
+    double orr = 0.0, oi = 0.0;
+    if (has_old) {
+        const double2 o = A.u[s.node];
+        orr = o.x;
+        oi = o.y;
+    }
+    dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+    nsum += ur * ur + ui * ui;
+    A.u[s.node] = make_double2(ur, ui);
+}
+
+// Interface update (eq. (2), sign read for consistency with b):
+// g_{r,s'} = -g_{l,s} - 2 i (omega/c) u_l on each shared side node; outer
+// sides get 0.  Cooperative over the workgroup, coalesced along sides.
+template <typename Real>
+__device__ void exchange(const SweepArgs<Real>& A, const SubDesc& d) {
+    const int nxl = d.nxl, nyl = d.nyl;
+    const int per = 2 * nyl + 2 * nxl;
+    for (int k = threadIdx.x; k < per; k += blockDim.x) {
+        int pos, node;
+        int64_t dst;
+        if (k < nyl) {
+            pos = k; node = k * nxl; dst = d.nbr_off[0];
+        } else if (k < 2 * nyl) {
+            pos = k - nyl; node = pos * nxl + nxl - 1; dst = d.nbr_off[1];
+        } else if (k < 2 * nyl + nxl) {
+            pos = k - 2 * nyl; node = pos; dst = d.nbr_off[2];
+        } else {
+            pos = k - 2 * nyl - nxl; node = (nyl - 1) * nxl + pos; dst = d.nbr_off[3];
+        }
+        if (dst >= 0) {
+            const double2 g = A.g_in[d.if_off + k];
+            const double K = A.kside[d.if_off + k];
+            const double2 u = A.u[d.node_off + node];
+            A.g_out[dst + pos] = make_double2(-g.x + 2.0 * K * u.y, -g.y - 2.0 * K * u.x);
+        } else {
+            A.g_out[d.if_off + k] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
+// Copy the subdomain's per-step tables into LDS as {cos, sin, kappa,
+// kappa_{+1/2}/omega} quadruples (one broadcast read per step).
+template <typename Real>
+__device__ __forceinline__ void stage_tables(const SweepArgs<Real>& A, const SubDesc& d, Real* tab) {
+    for (int nu = threadIdx.x; nu < d.nt; nu += blockDim.x) {
+        tab[4 * nu + 0] = A.cs[d.toff + nu];
+        tab[4 * nu + 1] = A.sn[d.toff + nu];
+        tab[4 * nu + 2] = A.kap[d.toff + nu];
+        tab[4 * nu + 3] = A.kaph[d.toff + nu];
+    }
+}
+
+// Coefficients of the assembled 1D reference stiffness row at node k of a
+// line of n_el elements, as a (2P+1)-point window centred on k (KL: the
+// reference element matrix in LDS, row-major).
+template <typename Real, int P>
+__device__ __forceinline__ void window_coeffs(Real (&w)[2 * P + 1], int k, int n_el,
+                                              const Real* KL) {
+#pragma unroll
+    for (int j = 0; j <= 2 * P; ++j) w[j] = Real(0);
+    const int e = k / P, a = k - e * P;
+    if (a == 0) {
+        if (e < n_el) {
+#pragma unroll
+            for (int q = 0; q <= P; ++q) w[P + q] += KL[q];
+        }
+        if (e > 0) {
+#pragma unroll
+            for (int q = 0; q <= P; ++q) w[q] += KL[P * (P + 1) + q];
+        }
+    } else {
+        // row a of element e couples the nodes e*P + q, q = 0..P, which sit
+        // at window offset q - a
+#pragma unroll
+        for (int j = 0; j <= 2 * P; ++j) {
+            const int q = j - P + a;
+            const int qq = q < 0 ? 0 : (q > P ? P : q);
+            const Real kv = KL[a * (P + 1) + qq];
+            w[j] = (q == qq) ? kv : Real(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PATCH layout
+// ---------------------------------------------------------------------------
+
+// LDS carve-up of the patch layout (in units of Real).  The edge lines GC
+// (right column) and GR (top row) carry kMaxP zeros on both ends so their
+// windows need no bounds checks.
+struct PatchLds {
+    int vc, vr, sx, sy, gc, gr, zr, corner, kl, tab, total;
+};
+
+__host__ __device__ inline PatchLds patch_lds(int mx, int my, int P, int nt_max) {
+    PatchLds L;
+    const int np = mx * my * P;
+    L.vc = 0;
+    L.vr = L.vc + np;
+    L.sx = L.vr + np;
+    L.sy = L.sx + np;
+    L.gc = L.sy + np;
+    L.gr = L.gc + my * P + 1 + 2 * kMaxP;
+    L.zr = L.gr + mx * P + 1 + 2 * kMaxP;
+    L.corner = L.zr + kMaxP;
+    L.kl = L.corner + 2;
+    L.tab = L.kl + (kMaxP + 1) * (kMaxP + 1);
+    L.tab = (L.tab + 3) & ~3;  // 4-aligned quadruples
+    L.total = L.tab + 4 * nt_max;
+    return L;
+}
+
+// Canonical index of the reference stiffness entry K[a][b]: K is symmetric
+// and centrosymmetric (K[a][b] = K[P-a][P-b]), so only the canonical entries
+// are ever loaded (6 distinct scalars at P = 3).
+template <int P>
+__host__ __device__ constexpr int kcan_a(int a, int b) {
+    return (a <= b ? a : b) <= P - (a <= b ? b : a) ? (a <= b ? a : b) : P - (a <= b ? b : a);
+}
+template <int P>
+__host__ __device__ constexpr int kcan_b(int a, int b) {
+    return (a <= b ? a : b) <= P - (a <= b ? b : a) ? (a <= b ? b : a) : P - (a <= b ? a : b);
+}
+
+// Thread context of the patch layout for one subdomain.
+template <typename Real, int P>
+struct PatchCtx {
+    bool hasP, hasE;
+    int ex, ey;
+    Real* VC; Real* VR; Real* SX; Real* SY; Real* GC; Real* GR; Real* CORN; const Real* TAB;
+    const Real* pR; const Real* pT; const Real* pL; const Real* pB;
+    // edge slot
+    bool e_col, e_corner, e_wcorner;
+    int ek, e_il, e_jl;
+    Real* e_pub;               // where the edge value is published
+    const Real* e_line;        // its own line, at its own index
+    const Real* e_perp;        // partial sum feeding the other direction
+    Real ew[2 * P + 1];        // window coefficients on its own line
+    const double (*K1)[kMaxP + 1];
+
+    __device__ __forceinline__ Real K(int a, int b) const {
+        return (Real)K1[kcan_a<P>(a, b)][kcan_b<P>(a, b)];
+    }
+
+    // Carve LDS, zero the padded lines, stage the element matrix.  The
+    // caller syncs before setup_windows and before any LDS read.
+    __device__ void setup(const SubDesc& d, Real* lds, const double (*K1_)[kMaxP + 1], int nt_max) {
+        K1 = K1_;
+        const int mx = d.mx, my = d.my, tid = threadIdx.x;
+        const PatchLds L = patch_lds(mx, my, P, nt_max);
+        VC = lds + L.vc; VR = lds + L.vr; SX = lds + L.sx; SY = lds + L.sy;
+        GC = lds + L.gc + kMaxP;
+        GR = lds + L.gr + kMaxP;
+        CORN = lds + L.corner;
+        TAB = lds + L.tab;
+        Real* ZR = lds + L.zr;
+        Real* KL = lds + L.kl;
+        for (int i = L.gc + tid; i < L.kl; i += blockDim.x) lds[i] = Real(0);
+        if (tid < (P + 1) * (P + 1)) KL[tid] = (Real)K1[tid / (P + 1)][tid % (P + 1)];
+        const int np = mx * my;
+        hasP = tid < np;
+        ex = hasP ? tid % mx : 0;
+        ey = hasP ? tid / mx : 0;
+        const int t = hasP ? tid : 0;
+        pR = (ex + 1 < mx) ? VC + (t + 1) * P : GC + ey * P;
+        pT = (ey + 1 < my) ? VR + (t + mx) * P : GR + ex * P;
+        pL = (ex > 0) ? SX + (t - 1) * P : ZR;
+        pB = (ey > 0) ? SY + (t - mx) * P : ZR;
+        const int mxP = mx * P, myP = my * P;
+        hasE = tid < mxP + myP + 1;
+        e_col = tid <= myP;
+        ek = hasE ? (e_col ? tid : tid - (myP + 1)) : 0;
+        e_corner = hasE && e_col && ek == myP;
+        e_wcorner = hasE && !e_col && ek == (mx - 1) * P;
+        if (e_col) {
+            e_il = mxP;
+            e_jl = ek;
+            e_pub = GC + ek;
+            e_line = GC + ek;
+            const int eyk = ek / P;
+            e_perp = e_corner ? CORN : SX + (eyk * mx + (mx - 1)) * P + (ek - eyk * P);
+        } else {
+            e_il = ek;
+            e_jl = myP;
+            e_pub = GR + ek;
+            e_line = GR + ek;
+            const int exk = ek / P;
+            e_perp = SY + ((my - 1) * mx + exk) * P + (ek - exk * P);
+        }
+    }
+
+    // Per-thread window coefficients (after K is staged and synced).
+    __device__ void setup_windows(const SubDesc& d, const Real* lds, int nt_max) {
+        const PatchLds L = patch_lds(d.mx, d.my, P, nt_max);
+        window_coeffs<Real, P>(ew, ek, e_col ? d.my : d.mx, lds + L.kl);
+        if (!hasE) {
+#pragma unroll
+            for (int j = 0; j <= 2 * P; ++j) ew[j] = Real(0);
+        }
+    }
+
+    // Publish the values other threads need: the a=0 column and b=0 row of
+    // the patch, and the edge node (the corner is stored in both lines).
+    __device__ __forceinline__ void publish(const Real (&p)[P][P], Real ep, int mx) {
+        if (hasP) {
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int b = 0; b < P; ++b) VC[t * P + b] = p[0][b];
+#pragma unroll
+            for (int a = 0; a < P; ++a) VR[t * P + a] = p[a][0];
+        }
+        if (hasE) {
+            *e_pub = ep;
+            if (e_corner) GR[mx * P] = ep;
+        }
+    }
+
+    // x-sum at (a, b) of this element (right vertex value pr = p(P, b)).
+    __device__ __forceinline__ Real xsum(const Real (&p)[P][P], int a, int b, Real pr) const {
+        Real s = K(a, P) * pr;
+#pragma unroll
+        for (int q = 0; q < P; ++q) s = fma(K(a, q), p[q][b], s);
+        return s;
+    }
+    // y-sum at (a, b) of this element (top vertex value pt = p(a, P)).
+    __device__ __forceinline__ Real ysum(const Real (&p)[P][P], int a, int b, Real pt) const {
+        Real s = K(b, P) * pt;
+#pragma unroll
+        for (int q = 0; q < P; ++q) s = fma(K(b, q), p[a][q], s);
+        return s;
+    }
+
+    // Edge node: sum along its own line (and the corner's x partial, written
+    // by the row thread at the last top-row vertex).
+    __device__ __forceinline__ Real edge_line_sum() const {
+        Real w[2 * P + 1];
+#pragma unroll
+        for (int j = 0; j <= 2 * P; ++j) w[j] = e_line[j - P];
+        Real s = Real(0);
+#pragma unroll
+        for (int j = 0; j <= 2 * P; ++j) s = fma(ew[j], w[j], s);
+        if (e_wcorner) {
+            Real c = Real(0);
+#pragma unroll
+            for (int q = 0; q <= P; ++q) c = fma(K(P, q), w[P + q], c);
+            *CORN = c;
+        }
+        return s;
+    }
+};
+
+// Coefficients of one patch.  Interior slots (a, b >= 1) lie on no
+// subdomain side, so alpha = 1 and the interface data contribute nothing
+// there; they only carry forcing when the sweep has a source term.
+template <typename Real, int P, bool HAS_SRC>
+struct PatchCoef {
+    Real bX[P][P], bY[P][P];
+    Real al[P][P];              // used on vertex-line slots only
+    Real bbr[P][P], bbi[P][P];  // vertex-line slots, and all slots with a source
+};
+
+template <int P>
+__host__ __device__ constexpr bool vline(int a, int b) { return a == 0 || b == 0; }
+
+template <typename Real, int P, bool HAS_SRC>
+__device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
+                                 double* red) {
+    PatchCtx<Real, P> C;
+    C.setup(d, lds, A.K1[P], A.nt_max);
+    stage_tables(A, d, lds + patch_lds(d.mx, d.my, P, A.nt_max).tab);
+    const int mx = d.mx, nxl = d.nxl;
+    PatchCoef<Real, P, HAS_SRC> cf;
+    Real p[P][P], pd[P][P], vr[P][P], vi[P][P];
+    const int64_t base = d.node_off + (int64_t)(C.ey * P) * nxl + C.ex * P;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            cf.bX[a][b] = cf.bY[a][b] = cf.al[a][b] = cf.bbr[a][b] = cf.bbi[a][b] = Real(0);
+            p[a][b] = pd[a][b] = vr[a][b] = vi[a][b] = Real(0);
+            if (C.hasP) {
+                const int64_t n = base + (int64_t)b * nxl + a;
+                cf.bX[a][b] = A.coef.betaX[n];
+                cf.bY[a][b] = A.coef.betaY[n];
+                if (vline<P>(a, b) || HAS_SRC) {
+                    const double be = (double)A.coef.beta[n];
+                    const double2 bb = assemble_b(A, d, C.ex * P + a, C.ey * P + b);
+                    cf.bbr[a][b] = (Real)(be * bb.x);
+                    cf.bbi[a][b] = (Real)(be * bb.y);
+                }
+                if (vline<P>(a, b)) cf.al[a][b] = A.coef.alpha[n];
+            }
+        }
+    Slot<Real> e;
+    slot_zero(e);
+    if (C.hasE) slot_load(e, A, d, C.e_il, C.e_jl);
+    __syncthreads();
+    C.setup_windows(d, lds, A.nt_max);
+
+    const Real sig = (Real)d.sigma;
+    const int nt = d.nt;
+    const Real* TAB = C.TAB;
+    const double pd0c = d.pd0c, pd0s = d.pd0s;
+    int it = 0;
+    for (int m = 0; m < A.max_wh; ++m) {
+        const Real k0 = TAB[2], kh0 = TAB[3];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                if (m > 0 && C.hasP) {
+                    const double2 u = A.u[base + (int64_t)b * nxl + a];
+                    p[a][b] = (Real)u.x;
+                    pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
+                } else {
+                    p[a][b] = Real(0);
+                    pd[a][b] = Real(0);
+                }
+                vr[a][b] = k0 * p[a][b];
+                vi[a][b] = kh0 * pd[a][b];
+            }
+        if (C.hasE) slot_init(e, A, d, m > 0, k0, kh0);
+
+        for (int nu = 1; nu < nt; ++nu) {
+            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
+            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
+            // p^{nu} = p^{nu-1} + sigma pdot^{nu-1/2}
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) p[a][b] = fma(sig, pd[a][b], p[a][b]);
+            e.p = fma(sig, e.pd, e.p);
+            C.publish(p, e.p, mx);
+            __syncthreads();
+
+            // pending velocity increments of the vertex-line slots
+            Real tv[P][P];
+            if (C.hasP) {
+                Real pr[P], pt[P];
+#pragma unroll
+                for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
+#pragma unroll
+                for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
+                // partial sums owed to the right / top neighbours' vertex lines
+#pragma unroll
+                for (int b = 0; b < P; ++b) C.SX[threadIdx.x * P + b] = C.xsum(p, P, b, pr[b]);
+#pragma unroll
+                for (int a = 0; a < P; ++a) C.SY[threadIdx.x * P + a] = C.ysum(p, a, P, pt[a]);
+#pragma unroll
+                for (int a = 0; a < P; ++a)
+#pragma unroll
+                    for (int b = 0; b < P; ++b) {
+                        const Real X = C.xsum(p, a, b, pr[b]);
+                        const Real Y = C.ysum(p, a, b, pt[a]);
+                        Real t;
+                        if (vline<P>(a, b) || HAS_SRC) {
+                            t = cf.bbr[a][b] * c;
+                            t = fma(cf.bbi[a][b], sv, t);
+                            t = fma(-cf.bX[a][b], X, t);
+                        } else {
+                            t = -cf.bX[a][b] * X;
+                        }
+                        t = fma(-cf.bY[a][b], Y, t);
+                        if (vline<P>(a, b)) {
+                            tv[a][b] = t;  // finished after the partials arrive
+                        } else {
+                            pd[a][b] += t;
+                            vr[a][b] = fma(k1, p[a][b], vr[a][b]);
+                            vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
+                        }
+                    }
+            }
+            Real eL = Real(0);
+            if (C.hasE) eL = C.edge_line_sum();
+            __syncthreads();
+            if (C.hasP) {
+#pragma unroll
+                for (int b = 0; b < P; ++b) tv[0][b] = fma(-cf.bX[0][b], C.pL[b], tv[0][b]);
+#pragma unroll
+                for (int a = 0; a < P; ++a) tv[a][0] = fma(-cf.bY[a][0], C.pB[a], tv[a][0]);
+#pragma unroll
+                for (int a = 0; a < P; ++a)
+#pragma unroll
+                    for (int b = 0; b < P; ++b)
+                        if (vline<P>(a, b)) {
+                            pd[a][b] = fma(cf.al[a][b], pd[a][b], tv[a][b]);
+                            vr[a][b] = fma(k1, p[a][b], vr[a][b]);
+                            vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
+                        }
+            }
+            if (C.hasE) {
+                const Real eP = *C.e_perp;
+                const Real eX = C.e_col ? eP : eL;
+                const Real eY = C.e_col ? eL : eP;
+                slot_step(e, eX, eY, c, sv, k1, k2);
+            }
+        }
+
+        double dsum = 0.0, nsum = 0.0;
+        if (C.hasP) {
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    const int64_t n = base + (int64_t)b * nxl + a;
+                    const double ur = d.two_over_nt * (double)vr[a][b];
+                    const double ui = d.two_over_nt * (double)vi[a][b];
+                    double orr = 0.0, oi = 0.0;
+                    if (m > 0) {
+                        const double2 o = A.u[n];
+                        orr = o.x;
+                        oi = o.y;
+                    }
+                    dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+                    nsum += ur * ur + ui * ui;
+                    A.u[n] = make_double2(ur, ui);
+                }
+        }
+        if (C.hasE) slot_finish(e, A, d, m > 0, dsum, nsum);
+        block_sum2(dsum, nsum, red);
+        it = m + 1;
+        if (!(dsum == dsum)) break;  // non-finite iterate: stop, reported by the host
+        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+    }
+    __threadfence_block();
+    __syncthreads();
+    exchange(A, d);
+    if (threadIdx.x == 0) A.wh_iters[item] = it;
+}
+
+template <typename Real, int P, int WG, bool HAS_SRC>
+__global__ void __launch_bounds__(WG) sweep_patch_kernel(const SweepArgs<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;                       // 2 * 16 doubles
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const SubDesc d = A.desc[item];
+        sweep_patch_item<Real, P, HAS_SRC>(A, d, item, lds, red);
+        __syncthreads();
+    }
+}
+
+// q = A p on stacked subdomain vectors with the patch routines of the
+// sweep (same publish / own-sum / partial-sum sequence).
+template <typename Real, int P, int WG>
+__global__ void __launch_bounds__(WG) apply_patch_kernel(const SweepArgs<Real> A,
+                                                         const Real* pin, Real* qout) {
+    extern __shared__ double smem_d[];
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    const SubDesc d = A.desc[blockIdx.x];
+    PatchCtx<Real, P> C;
+    C.setup(d, lds, A.K1[P], A.nt_max);
+    const int mx = d.mx, nxl = d.nxl;
+    const int64_t base = d.node_off + (int64_t)(C.ey * P) * nxl + C.ex * P;
+    Real p[P][P];
+    Real ep = Real(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) p[a][b] = C.hasP ? pin[base + (int64_t)b * nxl + a] : Real(0);
+    if (C.hasE) ep = pin[d.node_off + (int64_t)C.e_jl * nxl + C.e_il];
+    __syncthreads();
+    C.setup_windows(d, lds, A.nt_max);
+    C.publish(p, ep, mx);
+    __syncthreads();
+    Real X[P][P], Y[P][P];
+    if (C.hasP) {
+        Real pr[P], pt[P];
+#pragma unroll
+        for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
+#pragma unroll
+        for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
+#pragma unroll
+        for (int b = 0; b < P; ++b) C.SX[threadIdx.x * P + b] = C.xsum(p, P, b, pr[b]);
+#pragma unroll
+        for (int a = 0; a < P; ++a) C.SY[threadIdx.x * P + a] = C.ysum(p, a, P, pt[a]);
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                X[a][b] = C.xsum(p, a, b, pr[b]);
+                Y[a][b] = C.ysum(p, a, b, pt[a]);
+            }
+    }
+    Real eL = Real(0);
+    if (C.hasE) eL = C.edge_line_sum();
+    __syncthreads();
+    const double* wx = A.w1d + d.w_off;
+    const double* wy = wx + d.nxl;
+    if (C.hasP) {
+#pragma unroll
+        for (int b = 0; b < P; ++b) X[0][b] += C.pL[b];
+#pragma unroll
+        for (int a = 0; a < P; ++a) Y[a][0] += C.pB[a];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const int il = C.ex * P + a, jl = C.ey * P + b;
+                qout[base + (int64_t)b * nxl + a] =
+                    (Real)(d.sx_ref * wy[jl]) * X[a][b] + (Real)(d.sy_ref * wx[il]) * Y[a][b];
+            }
+    }
+    if (C.hasE) {
+        const Real eP = *C.e_perp;
+        const Real eX = C.e_col ? eP : eL;
+        const Real eY = C.e_col ? eL : eP;
+        qout[d.node_off + (int64_t)C.e_jl * nxl + C.e_il] =
+            (Real)(d.sx_ref * wy[C.e_jl]) * eX + (Real)(d.sy_ref * wx[C.e_il]) * eY;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// NODE layout (one DOF per thread)
+// ---------------------------------------------------------------------------
+
+// Padded LDS grid: (nxl + 2kMaxP) x (nyl + 2kMaxP) per buffer, two buffers,
+// then the element matrix and the per-step tables.
+__host__ __device__ inline int node_stride(int nxl) { return nxl + 2 * kMaxP; }
+__host__ __device__ inline int node_buf(int nxl, int nyl) {
+    return (nxl + 2 * kMaxP) * (nyl + 2 * kMaxP);
+}
+__host__ __device__ inline int node_tab_off(int nxl, int nyl) {
+    return (2 * node_buf(nxl, nyl) + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
+}
+
+template <typename Real, int P>
+struct NodeCtx {
+    bool has;
+    int il, jl, stride, pidx;
+    Real* buf0; Real* buf1; const Real* TAB;
+    Real wxk[2 * P + 1], wyk[2 * P + 1];
+
+    __device__ void setup(const SubDesc& d, Real* lds, const double (*K1)[kMaxP + 1]) {
+        const int nxl = d.nxl, nyl = d.nyl, tid = threadIdx.x;
+        const int nb = node_buf(nxl, nyl);
+        buf0 = lds;
+        buf1 = lds + nb;
+        Real* kl = lds + 2 * nb;
+        TAB = lds + node_tab_off(nxl, nyl);
+        for (int i = tid; i < 2 * nb; i += blockDim.x) lds[i] = Real(0);
+        if (tid < (P + 1) * (P + 1)) kl[tid] = (Real)K1[tid / (P + 1)][tid % (P + 1)];
+        __syncthreads();
+        has = tid < nxl * nyl;
+        il = has ? tid % nxl : 0;
+        jl = has ? tid / nxl : 0;
+        stride = node_stride(nxl);
+        pidx = (jl + kMaxP) * stride + il + kMaxP;
+        window_coeffs<Real, P>(wxk, il, d.mx, kl);
+        window_coeffs<Real, P>(wyk, jl, d.my, kl);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void sums(const Real* buf, Real& X, Real& Y) const {
+        Real sx = Real(0), sy = Real(0);
+#pragma unroll
+        for (int j = 0; j <= 2 * P; ++j) {
+            sx = fma(wxk[j], buf[pidx + j - P], sx);
+            sy = fma(wyk[j], buf[pidx + (j - P) * stride], sy);
+        }
+        X = sx;
+        Y = sy;
+    }
+};
+
+template <typename Real, int P>
+__device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
+                                double* red) {
+    NodeCtx<Real, P> C;
+    C.setup(d, lds, A.K1[P]);
+    stage_tables(A, d, lds + node_tab_off(d.nxl, d.nyl));
+    Slot<Real> s;
+    slot_zero(s);
+    if (C.has) slot_load(s, A, d, C.il, C.jl);
+    __syncthreads();
+    const Real sig = (Real)d.sigma;
+    const int nt = d.nt;
+    const Real* TAB = C.TAB;
+    int it = 0;
+    for (int m = 0; m < A.max_wh; ++m) {
+        if (C.has) slot_init(s, A, d, m > 0, TAB[2], TAB[3]);
+        for (int nu = 1; nu < nt; ++nu) {
+            Real* buf = (nu & 1) ? C.buf1 : C.buf0;
+            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
+            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
+            if (C.has) {
+                s.p = fma(sig, s.pd, s.p);
+                buf[C.pidx] = s.p;
+            }
+            __syncthreads();
+            if (C.has) {
+                Real X, Y;
+                C.sums(buf, X, Y);
+                slot_step(s, X, Y, c, sv, k1, k2);
+            }
+        }
+        double dsum = 0.0, nsum = 0.0;
+        if (C.has) slot_finish(s, A, d, m > 0, dsum, nsum);
+        block_sum2(dsum, nsum, red);
+        it = m + 1;
+        if (!(dsum == dsum)) break;
+        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+    }
+    __threadfence_block();
+    __syncthreads();
+    exchange(A, d);
+    if (threadIdx.x == 0) A.wh_iters[item] = it;
+}
+
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) sweep_node_kernel(const SweepArgs<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const SubDesc d = A.desc[item];
+        sweep_node_item<Real, P>(A, d, item, lds, red);
+        __syncthreads();
+    }
+}
+
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) apply_node_kernel(const SweepArgs<Real> A,
+                                                            const Real* pin, Real* qout) {
+    extern __shared__ double smem_d[];
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    const SubDesc d = A.desc[blockIdx.x];
+    NodeCtx<Real, P> C;
+    C.setup(d, lds, A.K1[P]);
+    if (C.has) C.buf0[C.pidx] = pin[d.node_off + (int64_t)C.jl * d.nxl + C.il];
+    __syncthreads();
+    if (C.has) {
+        Real X, Y;
+        C.sums(C.buf0, X, Y);
+        const double* wx = A.w1d + d.w_off;
+        const double* wy = wx + d.nxl;
+        qout[d.node_off + (int64_t)C.jl * d.nxl + C.il] =
+            (Real)(d.sx_ref * wy[C.jl]) * X + (Real)(d.sy_ref * wx[C.il]) * Y;
+    }
+}
+
+}  // namespace
+
+size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size) {
+    return 40 * sizeof(double) + (size_t)patch_lds(mx, my, P, nt_max).total * real_size;
+}
+
+size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size) {
+    return 40 * sizeof(double) + ((size_t)node_tab_off(nxl, nyl) + 4 * (size_t)nt_max) * real_size;
+}
+
+#define WDD_DISPATCH_P(P, CALL) \
+    switch (P) {                \
+        case 1: CALL(1); break; \
+        case 2: CALL(2); break; \
+        case 3: CALL(3); break; \
+        case 4: CALL(4); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+template <typename Real>
+hipError_t launch_sweep_patch(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    const bool src = a.Fre != nullptr && a.src != 0.0;
+#define L(PP, W, S) \
+    hipLaunchKernelGGL((sweep_patch_kernel<Real, PP, W, S>), dim3(a.n_items), dim3(wg), lds, s, a)
+#define L256(PP) if (src) L(PP, 256, true); else L(PP, 256, false)
+#define L512(PP) if (src) L(PP, 512, true); else L(PP, 512, false)
+    if (wg <= 256) {
+        WDD_DISPATCH_P(P, L256)
+    } else if (wg <= 512) {
+        WDD_DISPATCH_P(P, L512)
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef L
+#undef L256
+#undef L512
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_sweep_node(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+#define L(PP) hipLaunchKernelGGL((sweep_node_kernel<Real, PP>), dim3(a.n_items), dim3(wg), lds, s, a)
+    WDD_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_apply_patch(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                              hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    if (wg <= 256) {
+#define L(PP) \
+    hipLaunchKernelGGL((apply_patch_kernel<Real, PP, 256>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+        WDD_DISPATCH_P(P, L)
+#undef L
+    } else if (wg <= 512) {
+#define L(PP) \
+    hipLaunchKernelGGL((apply_patch_kernel<Real, PP, 512>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+        WDD_DISPATCH_P(P, L)
+#undef L
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                             hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+#define L(PP) \
+    hipLaunchKernelGGL((apply_node_kernel<Real, PP>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+    WDD_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep_patch<double>(const SweepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_sweep_patch<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_sweep_node<double>(const SweepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_sweep_node<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_apply_patch<double>(const SweepArgs<double>&, int, int, const double*,
+                                               double*, hipStream_t);
+template hipError_t launch_apply_patch<float>(const SweepArgs<float>&, int, int, const float*,
+                                              float*, hipStream_t);
+template hipError_t launch_apply_node<double>(const SweepArgs<double>&, int, int, const double*,
+                                              double*, hipStream_t);
+template hipError_t launch_apply_node<float>(const SweepArgs<float>&, int, int, const float*,
+                                             float*, hipStream_t);
+
+}  // namespace wdd

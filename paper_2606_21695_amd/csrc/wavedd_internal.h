@@ -1,0 +1,131 @@
+// Internal declarations shared by the host driver and the HIP kernels of
+// the wavedd library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wdd {
+
+constexpr int kMaxP = 4;           // largest supported polynomial degree
+constexpr int kMaxWG = 1024;       // largest workgroup
+
+// One subdomain work item of a sweep launch.  All offsets index the
+// per-node arrays (node_off) or the interface arrays (if_off, nbr_off).
+struct SubDesc {
+    int mx, my, P;       // elements per side, degree
+    int nxl, nyl;        // local node grid
+    int nt;              // leapfrog steps per period
+    int toff;            // offset of this subdomain's filter tables
+    int pad0;
+    int64_t node_off;    // first local node in the per-node arrays
+    int64_t w_off;       // first entry of its 1D weights: nxl along x, then nyl along y
+    int64_t if_off;      // first slot of this subdomain's 4 sides (g layout)
+    int64_t nbr_off[4];  // first slot of the neighbour side receiving each side, -1: outer
+    double sigma;        // leapfrog step sigma = sin(omega dt / 2) / (omega / 2)
+    double pd0c, pd0s;   // omega cos(pi/N_t), omega sin(pi/N_t): pdot^{1/2} from u
+    double two_over_nt;  // 2 / N_t
+    double sx_ref, sy_ref;  // 2/hx, 2/hy: reference-to-physical stiffness scales
+};
+
+// Per-node coefficient arrays of a sweep in the sweep precision `Real`.
+template <typename Real>
+struct NodeCoef {
+    const Real* alpha;   // (M - theta H) / (M + theta H)
+    const Real* betaX;   // beta * (2/hx) * Wy(jl): weight of the x-stiffness sum
+    const Real* betaY;   // beta * (2/hy) * Wx(il): weight of the y-stiffness sum
+    const Real* beta;    // sigma / (M + theta H)
+};
+
+template <typename Real>
+struct SweepArgs {
+    const SubDesc* desc;     // one per work item
+    int n_items;
+    NodeCoef<Real> coef;
+    const Real* Fre;         // area-weighted source (f, phi) per node, or null
+    const Real* Fim;
+    const double* w1d;       // physical lumped 1D weights (x then y) at desc.w_off
+    const double* kside;     // omega / c per interface slot
+    const Real* kap;         // kappa(nu)
+    const Real* kaph;        // kappa(nu + 1/2) / omega
+    const Real* cs;          // cos(2 pi nu / N_t)
+    const Real* sn;          // sin(2 pi nu / N_t)
+    const double2* g_in;     // interface data (g layout), FP64 complex
+    double2* g_out;          // updated interface data
+    double src;              // multiplier of the source term
+    double2* u;              // WaveHoltz iterate / result per node (FP64 complex)
+    int* wh_iters;           // per item: WaveHoltz iterations performed
+    double tau;              // inner tolerance (<= 0: fixed count)
+    int max_wh;              // iteration cap / fixed count
+    size_t lds_bytes;        // dynamic LDS per workgroup of the launch
+    int nt_max;              // largest N_t of the launch (sizes the LDS tables)
+    double K1[kMaxP + 1][kMaxP + 1][kMaxP + 1];  // K1[P][a][b]: reference D^T W D
+};
+
+// Launchers (defined in the .hip kernel sources).
+template <typename Real>
+hipError_t launch_sweep_patch(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
+template <typename Real>
+hipError_t launch_sweep_node(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
+template <typename Real>
+hipError_t launch_apply_patch(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                              hipStream_t s);
+template <typename Real>
+hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                             hipStream_t s);
+size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size);
+size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size);
+
+// FP64 helpers for the outer iteration (blas_kernels.hip).
+struct Blas {
+    double2* partial = nullptr;   // [max_blocks * (max_vecs)] complex partial sums
+    double2* result = nullptr;    // [max_vecs] reduced results
+    int max_blocks = 0, max_vecs = 0;
+};
+hipError_t blas_init(Blas& b, int max_vecs, hipStream_t s);
+void blas_free(Blas& b);
+// h[i] = <V_i, w> for i < k (V_i = V + i*ld), conjugate-linear in V_i.
+hipError_t blas_multidot(Blas& b, const double2* V, int64_t ld, int k, const double2* w, int64_t n,
+                         hipStream_t s);
+// w -= sum_i h[i] V_i, with h read from device memory (b.result) times `sign`.
+hipError_t blas_multiaxpy(Blas& b, const double2* V, int64_t ld, int k, double2* w, int64_t n,
+                          hipStream_t s);
+hipError_t blas_scale(double2* x, const double2* alpha_dev, int64_t n, int invert, hipStream_t s);
+// y = a*x + b*y (host scalars)
+hipError_t blas_axpby(double2 a, const double2* x, double2 b, double2* y, int64_t n, hipStream_t s);
+// y = sum_i c[i] V_i (host coefficients, copied to a device buffer first)
+hipError_t blas_combine(const double2* V, int64_t ld, int k, const double2* c_dev, double2* y,
+                        int64_t n, int accumulate, hipStream_t s);
+
+// Per-solve data movement kernels.
+hipError_t gather_source(const double* f_re, const double* f_im, const int* gidx,
+                         const double* area, int64_t n, void* Fre, void* Fim, int fp32,
+                         hipStream_t s);
+hipError_t embed_trace(const double* g_re, const double* g_im, const int64_t* trace_idx,
+                       int64_t n_if, double2* G, hipStream_t s);
+hipError_t glue_solution(const double2* usub, int Nx, int Ny, int P, int mx, int my, int sx,
+                         int sy, int64_t nloc, double* u_re, double* u_im, hipStream_t s);
+hipError_t mask_interface(double2* G, const int* is_iface, int64_t n_if, hipStream_t s);
+hipError_t split_complex(const double2* z, double* re, double* im, int64_t n, hipStream_t s);
+
+// Whole-domain operator y = S x (FP64) on the global node grid.
+struct OperatorArgs {
+    int Nx, Ny, P, nx, ny;
+    double sx_ref, sy_ref;        // 2/hx, 2/hy
+    const double* wx;             // assembled physical 1D weights along x (Nx)
+    const double* wy;             // along y (Ny)
+    const double* M;              // lumped mass per node (N)
+    const double* H;              // lumped boundary mass per node (N)
+    double omega;
+    double K1[kMaxP + 1][kMaxP + 1];
+};
+hipError_t launch_operator(const OperatorArgs& a, const double2* x, double2* y, hipStream_t s);
+// work[g] = (|b - S u|^2, |b|^2) per global node (f, g may be null).
+hipError_t launch_residual(const OperatorArgs& a, const double2* u, const double* f_re,
+                           const double* f_im, const double* g_re, const double* g_im,
+                           double2* work, hipStream_t s);
+// b.result[0] = sum of v (both components), deterministic.
+hipError_t blas_sum2(Blas& b, const double2* v, int64_t n, hipStream_t s);
+
+}  // namespace wdd

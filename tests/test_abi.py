@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point
+that include/wavedd.h declares, and rejects bad arguments before any device
+work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2606_21695_amd import wavedd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wavedd.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(dd_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_lists_binding_exports():
+    assert set(declared()) == set(wavedd.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = wavedd.load()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_options():
+    o = wavedd.dd_default_options()
+    assert o.precision == wavedd.DD_FP64 and o.restart == 50 and o.max_wh == 100
+    assert abs(o.cfl - 0.9) < 1e-15 and abs(o.tau_in - 1e-12) < 1e-27
+
+
+def _setup_rc(nx=4, ny=4, P=2, c=None, omega=3.0, sx=2, sy=2, **kw):
+    N = (nx * P + 1) * (ny * P + 1)
+    c = np.ones(N) if c is None else c
+    try:
+        wavedd.dd_setup(nx, ny, P, c, omega, sx, sy, **kw)
+    except wavedd.WaveddError as e:
+        return e.code, str(e)
+    return 0, ""
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(P=0), "degree"),
+    (dict(P=5), "degree"),
+    (dict(omega=0.0), "omega"),
+    (dict(omega=-1.0), "omega"),
+    (dict(sx=3), "partition"),
+    (dict(nx=0), "empty"),
+])
+def test_setup_rejects_bad_arguments(kw, needle):
+    rc, msg = _setup_rc(**kw)
+    assert rc == wavedd.DD_EINVAL and needle in msg
+
+
+def test_setup_rejects_nonpositive_wavespeed():
+    c = np.ones(81)
+    c[7] = 0.0
+    rc, msg = _setup_rc(c=c)
+    assert rc == wavedd.DD_EINVAL and "wavespeed[7]" in msg
+    c[7] = np.nan
+    rc, _ = _setup_rc(c=c)
+    assert rc == wavedd.DD_EINVAL
+
+
+def test_setup_rejects_bad_options():
+    for kw in (dict(precision=7), dict(restart=0), dict(cfl=1.5), dict(max_wh=0),
+               dict(nt_override=2), dict(layout=9), dict(outer=3)):
+        o = wavedd.dd_default_options(**kw)
+        rc, _ = _setup_rc(options=o)
+        assert rc == wavedd.DD_EINVAL, kw
+
+
+def test_setup_rejects_layout_that_does_not_fit():
+    # 40x40 elements at P=3 in one subdomain: 14641 nodes, 1600 patches
+    o = wavedd.dd_default_options(layout=wavedd.DD_LAYOUT_NODE)
+    rc, msg = _setup_rc(nx=40, ny=40, P=3, sx=1, sy=1, options=o)
+    assert rc == wavedd.DD_EINVAL and "1024" in msg
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = wavedd.load()
+    assert lib.dd_sizes(None, None, None, None, None, None) == wavedd.DD_EINVAL
+    assert lib.dd_layout(None, None, None) == wavedd.DD_EINVAL
+    lib.dd_destroy(None)

@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances (relative l2 over the stacked subdomain copies):
+* stiffness apply, FP64: 1e-13; FP32: 2e-6 (single rounding per term).
+* fixed-count WaveHoltz sweep iterates, FP64: 1e-11 (the GPU sums the
+  stiffness in a different order; the error after m periods of N_t steps stays
+  within a few hundred ulps of the solution); FP32: 1e-4 (bounded by
+  N_t * m * eps_32 * amplification).
+* converged sweep vs sparse LU, FP64: 1e-9 (inner tolerance 1e-12 times the
+  WaveHoltz contraction constant).
+* full solve vs the oracle DD at the same outer tolerance: 1e-10 in FP64
+  (spec bar); FP32 subdomain sweeps: 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import dd, sem
+from oracle import waveholtz as wh
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(W, nx, ny, P, sx, sy, omega, cfun, box=(0.0, 1.0, 0.0, 1.0), **opt):
+    o = W.dd_default_options(**opt)
+    N = (nx * P + 1) * (ny * P + 1)
+    probe = W.dd_setup(nx, ny, P, np.ones(N), omega, sx, sy, *box, options=o)
+    X, Y = W.dd_node_coords(probe)
+    W.dd_destroy(probe)
+    h = W.dd_setup(nx, ny, P, cfun(X, Y), omega, sx, sy, *box, options=o)
+    return h, X, Y
+
+
+def _oracle(nx, ny, P, sx, sy, omega, cfun, box=(0.0, 1.0, 0.0, 1.0)):
+    mesh = sem.Rect(nx, ny, P, *box)
+    X, Y = sem.node_coords(mesh)
+    dec = dd.Decomposition(mesh, dd.Partition(sx, sy), cfun(X, Y), omega)
+    return dec, X, Y
+
+
+def _cwave(X, Y):
+    return 1.0 + 0.35 * np.sin(5 * X + 0.3) * np.cos(4 * Y - 0.2)
+
+
+def _rel(a, b):
+    a, b = np.concatenate([np.ravel(x) for x in a]), np.concatenate([np.ravel(x) for x in b])
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SHAPES = [(6, 4, 3, 2, 2), (8, 8, 2, 2, 2), (4, 6, 1, 2, 3), (4, 4, 4, 2, 1), (3, 5, 3, 1, 1)]
+LAYOUTS = [1, 2]  # DD_LAYOUT_NODE, DD_LAYOUT_PATCH
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stiffness_apply(gpu_lib, shape, layout, prec):
+    W = gpu_lib
+    nx, ny, P, sx, sy = shape
+    h, _, _ = _setup(W, nx, ny, P, sx, sy, 7.0, _cwave, precision=prec, layout=layout)
+    dec, _, _ = _oracle(nx, ny, P, sx, sy, 7.0, _cwave)
+    print(f"stiffness shape={shape} layout={layout} prec={prec}", flush=True)
+    rng = np.random.default_rng(sum(shape) + 10 * layout)
+    p = rng.standard_normal(dec.L * dec.nxl * dec.nyl)
+    q = W.dd_apply_stiffness(h, p)
+    n = dec.nxl * dec.nyl
+    ref = [dec.subs[l]["A"] @ p[l * n:(l + 1) * n] for l in range(dec.L)]
+    W.dd_destroy(h)
+    assert _rel([q], ref) < (1e-13 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_stiffness_unit_vectors(gpu_lib, layout):
+    """A applied to every unit vector of a one-subdomain mesh equals the
+    oracle's assembled matrix entry by entry."""
+    W = gpu_lib
+    h, _, _ = _setup(W, 3, 2, 3, 1, 1, 5.0, _cwave, layout=layout)
+    dec, _, _ = _oracle(3, 2, 3, 1, 1, 5.0, _cwave)
+    A = dec.subs[0]["A"].toarray()
+    n = A.shape[0]
+    cols = np.array([W.dd_apply_stiffness(h, np.eye(n)[k]) for k in range(n)]).T
+    W.dd_destroy(h)
+    assert np.abs(cols - A).max() < 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_time_steps_match_oracle(gpu_lib, shape):
+    W = gpu_lib
+    nx, ny, P, sx, sy = shape
+    for om in (3.0, 11.0, 40.0):
+        h, _, _ = _setup(W, nx, ny, P, sx, sy, om, _cwave)
+        dec, _, _ = _oracle(nx, ny, P, sx, sy, om, _cwave)
+        nt = W.dd_time_steps(h)
+        W.dd_destroy(h)
+        assert list(nt) == wh.subdomain_steps(dec), (shape, om)
+
+
+def _random_g(dec, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(dec.n_if) + 1j * rng.standard_normal(dec.n_if)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_fixed_iterations(gpu_lib, shape, layout, prec):
+    """One DD cycle with exactly m WaveHoltz iterations from u = 0: iterates
+    and interface output against the oracle's WaveHoltz (Algorithm 1)."""
+    W = gpu_lib
+    nx, ny, P, sx, sy = shape
+    om, m = 9.0, 3
+    h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, precision=prec, layout=layout,
+                       tau_in=0.0, max_wh=m)
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, om, _cwave)
+    print(f"sweep shape={shape} layout={layout} prec={prec}", flush=True)
+    g = _random_g(dec, sum(shape))
+    f = np.exp(-((X - 0.4) ** 2 + (Y - 0.55) ** 2) / 0.02)
+    fl = np.exp(-((Xl - 0.4) ** 2 + (Yl - 0.55) ** 2) / 0.02)
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, fl, 1.0)
+    W.dd_destroy(h)
+    g_ref, u_ref = dec.sweep(g, f, 1.0, wh.make_solver(dec, fixed_iters=m))
+    assert (its == m).all()
+    tol = 1e-11 if prec == 0 else 1e-4
+    assert _rel([u_gpu], u_ref) < tol
+    assert _rel([g_gpu], [g_ref]) < tol
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_sweep_converged_matches_lu(gpu_lib, layout):
+    W = gpu_lib
+    nx, ny, P, sx, sy = 8, 8, 2, 2, 2
+    h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, 10.0, _cwave, layout=layout, tau_in=1e-12)
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, 10.0, _cwave)
+    g = _random_g(dec, 5)
+    f = np.exp(-((X - 0.3) ** 2 + (Y - 0.6) ** 2) / (2 * 0.05 ** 2))
+    fl = np.exp(-((Xl - 0.3) ** 2 + (Yl - 0.6) ** 2) / (2 * 0.05 ** 2))
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, fl, 1.0)
+    W.dd_destroy(h)
+    g_ref, u_ref = dec.sweep(g, f, 1.0)
+    assert its.max() < 100
+    assert _rel([u_gpu], u_ref) < 1e-9
+    assert _rel([g_gpu], [g_ref]) < 1e-9
+
+
+def test_sweep_is_deterministic(gpu_lib):
+    W = gpu_lib
+    h, Xl, Yl = _setup(W, 8, 8, 3, 2, 2, 12.0, _cwave, tau_in=1e-10)
+    dec, _, _ = _oracle(8, 8, 3, 2, 2, 12.0, _cwave)
+    g = _random_g(dec, 9)
+    a = W.dd_sweep(h, g, None, 0.0)
+    b = W.dd_sweep(h, g, None, 0.0)
+    W.dd_destroy(h)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def _c1_pair(W, **opt):
+    import workloads
+    wl = workloads.c1()
+    h, Xl, Yl = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, **opt)
+    dec, X, Y = _oracle(wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c)
+    return wl, h, Xl, Yl, dec, X, Y
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_solve_c1_fp64_matches_oracle_dd(gpu_lib, layout):
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, layout=layout, tau_in=1e-12)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol)
+    us_ref, info = dd.solve_dd(dec, wl.f(X, Y), tol=wl.tol)
+    W.dd_destroy(h)
+    print(f"c1 gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
+    assert st["outer_iters"] == info["iters"]
+    assert _rel([u], [dec.glue(us_ref)]) < 1e-10
+    assert st["true_rel_residual"] < 2 * wl.tol
+
+
+def test_solve_c1_tight_matches_global_lu(gpu_lib):
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, tau_in=1e-13)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, 1e-12)
+    u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
+    rel_res = W.dd_residual(h, u, wl.f(Xl, Yl))
+    W.dd_destroy(h)
+    assert _rel([u], [u_lu]) < 1e-10
+    assert rel_res < 1e-10
+
+
+def test_solve_c1_fp32_inner(gpu_lib):
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-7)
+    u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, allow_notconv=True)
+    W.dd_destroy(h)
+    u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
+    err = _rel([u], [u_lu])
+    print(f"c1 fp32 err={err:.3e} iters={st['outer_iters']} true_res={st['true_rel_residual']:.2e}")
+    assert err < 1e-6
+
+
+def test_plane_wave_boundary_data(gpu_lib):
+    """Outer impedance data g = i k (d.n - 1) u of an exact plane wave."""
+    W = gpu_lib
+    nx, P, om = 8, 3, 12.0
+    h, Xl, Yl = _setup(W, nx, nx, P, 2, 4, om, lambda X, Y: np.ones_like(X))
+    mesh = sem.Rect(nx, nx, P)
+    ue, g = sem.plane_wave(mesh, om, 1.0, (np.cos(1.1), np.sin(1.1)))
+    u, st, _ = W.dd_solve(h, None, g, 1e-12)
+    u_lu = sem.solve(mesh, np.ones(mesh.N), om, np.zeros(mesh.N), g)
+    W.dd_destroy(h)
+    assert _rel([u], [u_lu]) < 1e-9
+    assert _rel([u], [ue]) < 1e-3
+
+
+def test_single_subdomain_is_one_sweep(gpu_lib):
+    W = gpu_lib
+    h, Xl, Yl = _setup(W, 6, 6, 2, 1, 1, 8.0, _cwave)
+    dec, X, Y = _oracle(6, 6, 2, 1, 1, 8.0, _cwave)
+    f = np.cos(3 * X) * Y
+    u, st, _ = W.dd_solve(h, np.cos(3 * Xl) * Yl, None, 1e-10)
+    W.dd_destroy(h)
+    assert st["outer_iters"] == 0
+    assert _rel([u], [sem.solve(dec.mesh, dec.c, 8.0, f)]) < 1e-9
+
+
+def test_max_iter_reports_not_converged(gpu_lib):
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W)
+    u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, 1e-12, max_iter=2, allow_notconv=True)
+    W.dd_destroy(h)
+    assert rc == W.DD_ENOTCONV
+    assert st["outer_iters"] == 2 and np.isfinite(u).all()
+
+
+def test_operator_and_residual_kernels(gpu_lib):
+    import torch
+    W = gpu_lib
+    h, Xl, Yl = _setup(W, 5, 7, 3, 1, 1, 6.0, _cwave)
+    mesh = sem.Rect(5, 7, 3)
+    X, Y = sem.node_coords(mesh)
+    S, _, _, _ = sem.system(mesh, _cwave(X, Y), 6.0)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(mesh.N) + 1j * rng.standard_normal(mesh.N)
+    xt = torch.from_numpy(np.stack([x.real, x.imag], 1).ravel()).cuda()
+    yt = torch.empty_like(xt)
+    W.dd_apply_operator_device(h, xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    y = y[0::2] + 1j * y[1::2]
+    ref = S @ x
+    f = rng.standard_normal(mesh.N)
+    rel = W.dd_residual(h, x, f)
+    b = sem.load(mesh, f)
+    W.dd_destroy(h)
+    assert np.linalg.norm(y - ref) < 1e-13 * np.linalg.norm(ref)
+    assert abs(rel - np.linalg.norm(b - ref) / np.linalg.norm(b)) < 1e-12 * rel
+
+
+def test_state_roundtrip(gpu_lib):
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol)
+    G = W.dd_get_state(h)
+    W.dd_set_state(h, G)
+    assert np.array_equal(W.dd_get_state(h), G)
+    W.dd_destroy(h)
