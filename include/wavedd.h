@@ -93,6 +93,9 @@ typedef struct {
     int restart;     /* GMRES restart length m */
     int nt_override; /* > 0: use this many time steps per period in every subdomain */
     double cfl;      /* safety factor s in (0, 1] of the time-step rule */
+    int refine;      /* DD_FP32 with GMRES: FP64 iterative-refinement steps (0 = none):
+                        corrections solved with FP32 sweeps, residuals and u from FP64
+                        sweeps with inner tolerance clamp(0.01 tol, 1e-13, 1e-8) */
 } dd_options;
 
 typedef struct {
@@ -106,10 +109,12 @@ typedef struct {
     double dof_updates;         /* sum over sweeps/subdomains of nloc*(N_t-1)*iterations */
     double sweep_seconds;       /* device time inside sweep launches */
     double seconds;             /* wall time of the call */
+    int refine_steps;           /* FP64 refinement steps taken (FP32 handles) */
+    int fp64_sweeps;            /* FP64 sweeps of a refined FP32 solve */
 } dd_stats;
 
 /* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
- * no N_t override, cfl 0.9. */
+ * no N_t override, cfl 0.9, refine 4. */
 int dd_default_options(dd_options* opt);
 
 /* Set up a problem (Sec. II-IV): mesh, degree P in [1, 4], wavespeed c > 0

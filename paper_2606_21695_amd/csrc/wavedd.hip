@@ -210,21 +210,25 @@ struct dd_handle {
     int nt_max = 0;
     std::vector<wdd::SubDesc> desc;
     int layout = DD_LAYOUT_PATCH, wg = 256;
-    size_t lds_bytes = 0;
     int dev = 0;
     hipStream_t stream = nullptr;
     // device data
     DBuf<wdd::SubDesc> d_desc;
-    DBuf<char> d_coef;               // alpha, betaX, betaY, beta in sweep precision
-    DBuf<char> d_tab;                // kap, kaph, cs, sn in sweep precision
+    // per-precision sweep data: [0] FP64 (always), [1] FP32 (FP32 handles)
+    struct PrecBuf {
+        DBuf<char> coef;             // alpha, betaX, betaY, beta
+        DBuf<char> tab;              // kap, kaph, cs, sn
+        DBuf<char> F;                // Fre, Fim (per solve)
+        size_t lds_bytes = 0;
+        bool present = false;
+    } pb[2];
     int64_t tab_len = 0;
-    DBuf<char> d_F;                  // Fre, Fim in sweep precision
     DBuf<double> d_w1d, d_kside, d_area;
     DBuf<int> d_gidx, d_iters, d_is_iface;
     DBuf<int64_t> d_trace_idx;
     DBuf<double2> d_u;               // stacked subdomain iterate
     DBuf<double2> d_V;               // GMRES basis (restart + 1) x ld
-    DBuf<double2> d_G, d_h, d_tmp, d_g0, d_r, d_coefs;
+    DBuf<double2> d_G, d_h, d_tmp, d_g0, d_r, d_coefs, d_D, d_res;
     DBuf<double> d_fre, d_fim, d_gre, d_gim, d_ure, d_uim;  // staging for host API
     DBuf<double> d_wxg, d_wyg, d_Mg, d_Hg;                 // global operator data
     DBuf<double2> d_work;            // N complex scratch
@@ -241,25 +245,28 @@ struct dd_handle {
 namespace {
 
 size_t real_size(const dd_handle* h) { return h->opt.precision == DD_FP32 ? 4 : 8; }
+size_t prec_size(int prec) { return prec == DD_FP32 ? 4 : 8; }
+int prec_index(int prec) { return prec == DD_FP32 ? 1 : 0; }
 
 template <typename Real>
 wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out, double src,
-                               bool with_f) {
+                               bool with_f, double tau, int max_wh) {
+    const dd_handle::PrecBuf& B = h->pb[sizeof(Real) == 4 ? 1 : 0];
     wdd::SweepArgs<Real> a{};
     a.desc = h->d_desc.p;
     a.n_items = (int)h->L;
-    Real* coef = reinterpret_cast<Real*>(h->d_coef.p);
+    Real* coef = reinterpret_cast<Real*>(B.coef.p);
     const int64_t n = h->L * h->nloc;
     a.coef.alpha = coef;
     a.coef.betaX = coef + n;
     a.coef.betaY = coef + 2 * n;
     a.coef.beta = coef + 3 * n;
-    Real* F = reinterpret_cast<Real*>(h->d_F.p);
+    Real* F = reinterpret_cast<Real*>(B.F.p);
     a.Fre = with_f ? F : nullptr;
     a.Fim = with_f ? F + n : nullptr;
     a.w1d = h->d_w1d.p;
     a.kside = h->d_kside.p;
-    Real* tab = reinterpret_cast<Real*>(h->d_tab.p);
+    Real* tab = reinterpret_cast<Real*>(B.tab.p);
     a.kap = tab;
     a.kaph = tab + h->tab_len;
     a.cs = tab + 2 * h->tab_len;
@@ -269,9 +276,9 @@ wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out
     a.src = src;
     a.u = h->d_u.p;
     a.wh_iters = h->d_iters.p;
-    a.tau = h->opt.tau_in;
-    a.max_wh = h->opt.max_wh;
-    a.lds_bytes = h->lds_bytes;
+    a.tau = tau;
+    a.max_wh = max_wh;
+    a.lds_bytes = B.lds_bytes;
     a.nt_max = h->nt_max;
     std::memcpy(a.K1, h->K1all, sizeof(a.K1));
     return a;
@@ -283,37 +290,41 @@ int patch_threads(const dd_handle* h) {
     return std::max(h->mx * h->my, h->mx * h->P + h->my * h->P + 1);
 }
 
-void layout_config(dd_handle* h, int layout) {
-    h->layout = layout;
-    if (layout == DD_LAYOUT_NODE) {
-        h->wg = ((h->nxl * h->nyl + 63) / 64) * 64;
-        h->lds_bytes = wdd::node_lds_bytes(h->nxl, h->nyl, h->nt_max, real_size(h));
-    } else {
-        h->wg = ((patch_threads(h) + 63) / 64) * 64;
-        h->lds_bytes = wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, real_size(h));
-    }
+size_t layout_lds(const dd_handle* h, int layout, int prec) {
+    const size_t rs = prec_size(prec);
+    if (layout == DD_LAYOUT_NODE) return wdd::node_lds_bytes(h->nxl, h->nyl, h->nt_max, rs);
+    return wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, rs);
 }
 
-bool layout_fits(const dd_handle* h, int layout) {
+void layout_config(dd_handle* h, int layout) {
+    h->layout = layout;
     if (layout == DD_LAYOUT_NODE)
-        return h->nxl * h->nyl <= 1024 &&
-               wdd::node_lds_bytes(h->nxl, h->nyl, h->nt_max, real_size(h)) <= kLdsLimit;
-    return patch_threads(h) <= 512 &&
-           wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, real_size(h)) <= kLdsLimit;
+        h->wg = ((h->nxl * h->nyl + 63) / 64) * 64;
+    else
+        h->wg = ((patch_threads(h) + 63) / 64) * 64;
+    for (int prec : {DD_FP64, DD_FP32})
+        h->pb[prec_index(prec)].lds_bytes = layout_lds(h, layout, prec);
+}
+
+// Fits in one workgroup for every precision the handle carries (FP64
+// always, for the refinement residuals of FP32 handles too).
+bool layout_fits(const dd_handle* h, int layout) {
+    const bool threads_ok = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl <= 1024 : patch_threads(h) <= 512;
+    return threads_ok && layout_lds(h, layout, DD_FP64) <= kLdsLimit;
 }
 
 // One sweep launch: g_out = sweep(g_in, src), u = subdomain solutions.
 int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
-              bool timed) {
+              bool timed, int prec, double tau, int max_wh) {
     hipStream_t s = h->stream;
     if (timed) HIPCHK(hipEventRecord(h->ev0, s));
     hipError_t e;
-    if (h->opt.precision == DD_FP32) {
-        auto a = make_args<float>(h, g_in, g_out, src, with_f);
+    if (prec == DD_FP32) {
+        auto a = make_args<float>(h, g_in, g_out, src, with_f, tau, max_wh);
         e = h->layout == DD_LAYOUT_NODE ? wdd::launch_sweep_node<float>(a, h->P, h->wg, s)
                                         : wdd::launch_sweep_patch<float>(a, h->P, h->wg, s);
     } else {
-        auto a = make_args<double>(h, g_in, g_out, src, with_f);
+        auto a = make_args<double>(h, g_in, g_out, src, with_f, tau, max_wh);
         e = h->layout == DD_LAYOUT_NODE ? wdd::launch_sweep_node<double>(a, h->P, h->wg, s)
                                         : wdd::launch_sweep_patch<double>(a, h->P, h->wg, s);
     }
@@ -328,6 +339,7 @@ int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, boo
         h->st.sweep_seconds += ms * 1e-3;
     }
     h->st.sweeps += 1;
+    if (prec == DD_FP64 && h->opt.precision == DD_FP32) h->st.fp64_sweeps += 1;
     for (int64_t l = 0; l < h->L; ++l) {
         const int it = h->iters_host[l];
         h->st.wh_iters_total += it;
@@ -335,6 +347,13 @@ int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, boo
         h->st.dof_updates += (double)h->nloc * (h->nt[l] - 1) * it;
     }
     return DD_OK;
+}
+
+// Sweep in the handle's own precision and inner tolerance.
+int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
+              bool timed) {
+    return run_sweep(h, g_in, g_out, src, with_f, timed, h->opt.precision, h->opt.tau_in,
+                     h->opt.max_wh);
 }
 
 // Hermitian inner products <V_i, w>, i < k, into host array out (device
@@ -362,34 +381,33 @@ int axpby(dd_handle* h, cplx a, const double2* x, cplx b, double2* y) {
 }
 
 
-// w = v - T v  (T: sweep with sources off); w must not alias v.
+// w = v - T v  (T: sweep with sources off, in the handle's precision);
+// w must not alias v.
 int matvec(dd_handle* h, const double2* v, double2* w) {
     CHK(run_sweep(h, v, w, 0.0, false, true));
     return axpby(h, cplx(1.0, 0.0), v, cplx(-1.0, 0.0), w);
 }
 
-// Restarted GMRES(m) on (I - T) G = h from G = 0 (the Krylov method of the
-// outer iteration, Sec. III last paragraph).  Arnoldi with classical
+// Restarted GMRES(m) for (I - T) x = rhs from x = 0 (the Krylov method of
+// the outer iteration, Sec. III last paragraph).  Arnoldi with classical
 // Gram-Schmidt applied twice (two block reductions per step instead of j+1
-// sequential ones), complex Givens rotations on the host.
-int gmres(dd_handle* h, double tol, int max_iter, double hnorm) {
+// sequential ones), complex Givens rotations on the host.  Stops when the
+// recursive residual <= tol * rnorm0 or after max_iter matvecs; returns the
+// iterations and the recursive relative residual.
+int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double tol, int max_iter,
+          int* its_out, double* rel_out) {
     const int m = h->opt.restart;
     const int64_t n = h->n_if, ld = h->ld;
     double2* V = h->d_V.p;
-    double2* G = h->d_G.p;
-    HIPCHK(hipMemsetAsync(G, 0, sizeof(double2) * n, h->stream));
-    h->st.outer_iters = 0;
-    h->st.rel_residual = 1.0;
-    if (hnorm == 0.0) {
-        h->st.rel_residual = 0.0;
-        return DD_OK;
-    }
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * n, h->stream));
+    *its_out = 0;
+    *rel_out = rnorm0 == 0.0 ? 0.0 : 1.0;
+    if (rnorm0 == 0.0 || max_iter <= 0) return DD_OK;
     std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
     std::vector<double> cs(m);
     std::vector<cplx> h1(m + 1), h2(m + 1);
-    HIPCHK(hipMemcpyAsync(h->d_r.p, h->d_h.p, sizeof(double2) * n, hipMemcpyDeviceToDevice,
-                          h->stream));
-    double beta = hnorm;
+    HIPCHK(hipMemcpyAsync(h->d_r.p, rhs, sizeof(double2) * n, hipMemcpyDeviceToDevice, h->stream));
+    double beta = rnorm0;
     int its = 0;
     double rel = 1.0;
     while (true) {
@@ -429,32 +447,33 @@ int gmres(dd_handle* h, double tol, int max_iter, double hnorm) {
             H[(size_t)(j + 1) * m + j] = 0.0;
             g[j + 1] = -std::conj(sn[j]) * g[j];
             g[j] = cs[j] * g[j];
-            rel = std::abs(g[j + 1]) / hnorm;
+            rel = std::abs(g[j + 1]) / rnorm0;
             k = j + 1;
             if (!std::isfinite(rel)) return fail(DD_ENAN, "non-finite outer residual");
-            if (rel <= tol || its >= max_iter) break;
+            if (rel <= tol || its >= max_iter || hn == 0.0) break;
         }
         for (int i = k - 1; i >= 0; --i) {
-            cplx s = g[i];
-            for (int q = i + 1; q < k; ++q) s -= H[(size_t)i * m + q] * y[q];
-            y[i] = s / H[(size_t)i * m + i];
+            cplx sacc = g[i];
+            for (int q = i + 1; q < k; ++q) sacc -= H[(size_t)i * m + q] * y[q];
+            y[i] = sacc / H[(size_t)i * m + i];
         }
         std::vector<double2> yc(k);
         for (int i = 0; i < k; ++i) yc[i] = make_double2(y[i].real(), y[i].imag());
         HIPCHK(hipMemcpyAsync(h->d_coefs.p, yc.data(), sizeof(double2) * k, hipMemcpyHostToDevice,
                               h->stream));
-        HIPCHK(wdd::blas_combine(V, ld, k, h->d_coefs.p, G, n, 1, h->stream));
+        HIPCHK(wdd::blas_combine(V, ld, k, h->d_coefs.p, x, n, 1, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
-        h->st.outer_iters = its;
-        h->st.rel_residual = rel;
         if (rel <= tol || its >= max_iter) break;
-        // r = h - (G - T G)
-        CHK(matvec(h, G, h->d_r.p));
-        CHK(axpby(h, cplx(1.0), h->d_h.p, cplx(-1.0), h->d_r.p));
+        // r = rhs - (x - T x)
+        CHK(matvec(h, x, h->d_r.p));
+        CHK(axpby(h, cplx(1.0), rhs, cplx(-1.0), h->d_r.p));
         beta = norm(h, h->d_r.p);
         if (!std::isfinite(beta)) return fail(DD_ENAN, "non-finite outer residual");
-        if (beta == 0.0) break;
+        rel = beta / rnorm0;
+        if (beta == 0.0 || rel <= tol) break;
     }
+    *its_out = its;
+    *rel_out = rel;
     return DD_OK;
 }
 
@@ -487,23 +506,80 @@ void reset_stats(dd_handle* h) {
     h->st.nt_max = *std::max_element(h->nt.begin(), h->nt.end());
 }
 
+// tmp = sweep(G + g0, sources on) = T G + h in precision prec (u left in
+// d_u); returns ||tmp - G|| / hnorm, the outer residual of G.
+int residual_sweep(dd_handle* h, bool with_f, int prec, double tau, double hnorm, double* rel) {
+    CHK(axpby(h, cplx(1.0), h->d_g0.p, cplx(1.0), h->d_G.p));    // G += g0 (disjoint slots)
+    CHK(run_sweep(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, true, prec, tau, h->opt.max_wh));
+    CHK(axpby(h, cplx(-1.0), h->d_g0.p, cplx(1.0), h->d_G.p));   // G -= g0
+    CHK(axpby(h, cplx(-1.0), h->d_G.p, cplx(1.0), h->d_tmp.p));  // tmp = T G + h - G
+    const double r = norm(h, h->d_tmp.p);
+    if (!std::isfinite(r)) return fail(DD_ENAN, "non-finite outer residual");
+    *rel = hnorm > 0.0 ? r / hnorm : 0.0;
+    return DD_OK;
+}
+
+// Inner tolerance of the FP64 residual sweeps of a refined FP32 solve.
+double refine_tau(double tol) { return std::min(1e-8, std::max(1e-13, 0.01 * tol)); }
+
+// FP32 sweeps with FP64 iterative refinement on the interface system:
+// G += GMRES_fp32((I - T) d = r); r = h - (I - T) G with an FP64 sweep.
+int solve_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
+    const double tau64 = refine_tau(tol);
+    CHK(run_sweep(h, h->d_g0.p, h->d_h.p, 1.0, with_f, true, DD_FP64, tau64, h->opt.max_wh));
+    const double hnorm = norm(h, h->d_h.p);
+    if (!std::isfinite(hnorm)) return fail(DD_ENAN, "non-finite right-hand side");
+    HIPCHK(hipMemsetAsync(h->d_G.p, 0, sizeof(double2) * h->n_if, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_h.p, sizeof(double2) * h->n_if,
+                          hipMemcpyDeviceToDevice, h->stream));
+    double rnorm = hnorm;
+    int its_total = 0;
+    double rel = hnorm > 0.0 ? 1.0 : 0.0;
+    bool have_u = false;
+    for (int k = 0; k <= h->opt.refine && rel > tol && its_total < max_iter; ++k) {
+        // inner accuracy: a fixed reduction, or whatever reaches tol
+        const double inner = std::max(1e-4, tol * hnorm / rnorm);
+        int its = 0;
+        double irel = 0.0;
+        CHK(gmres(h, h->d_res.p, h->d_D.p, rnorm, inner, max_iter - its_total, &its, &irel));
+        its_total += its;
+        CHK(axpby(h, cplx(1.0), h->d_D.p, cplx(1.0), h->d_G.p));
+        CHK(residual_sweep(h, with_f, DD_FP64, tau64, hnorm, &rel));
+        HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_tmp.p, sizeof(double2) * h->n_if,
+                              hipMemcpyDeviceToDevice, h->stream));
+        rnorm = rel * hnorm;
+        h->st.refine_steps = k + 1;
+        have_u = true;
+    }
+    if (!have_u) CHK(residual_sweep(h, with_f, DD_FP64, tau64, hnorm, &rel));
+    h->st.outer_iters = its_total;
+    h->st.rel_residual = rel;
+    h->st.true_rel_residual = rel;
+    h->has_state = true;
+    return DD_OK;
+}
+
 // Full solve with the device inputs staged: d_g0 (embedded boundary trace)
 // and F (source).  Leaves the stacked u in d_u and G in d_G.
 int solve_core(dd_handle* h, bool with_f, double tol, int max_iter) {
+    if (h->opt.precision == DD_FP32 && h->opt.refine > 0 && h->opt.outer == DD_OUTER_GMRES)
+        return solve_refined(h, with_f, tol, max_iter);
     CHK(run_sweep(h, h->d_g0.p, h->d_h.p, 1.0, with_f, true));  // h = sweep(g_phys, src)
     const double hnorm = norm(h, h->d_h.p);
     if (!std::isfinite(hnorm)) return fail(DD_ENAN, "non-finite right-hand side");
-    if (h->opt.outer == DD_OUTER_FIXED)
+    if (h->opt.outer == DD_OUTER_FIXED) {
         CHK(fixed_point(h, tol, max_iter, hnorm));
-    else
-        CHK(gmres(h, tol, max_iter, hnorm));
+    } else {
+        int its = 0;
+        double rel = 0.0;
+        CHK(gmres(h, h->d_h.p, h->d_G.p, hnorm, tol, max_iter, &its, &rel));
+        h->st.outer_iters = its;
+        h->st.rel_residual = rel;
+    }
     // final sweep with G + g_phys and sources: u, and T G + h for the true residual
-    CHK(axpby(h, cplx(1.0), h->d_g0.p, cplx(1.0), h->d_G.p));    // G += g0 (disjoint slots)
-    CHK(run_sweep(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, true));
-    CHK(axpby(h, cplx(-1.0), h->d_g0.p, cplx(1.0), h->d_G.p));   // G -= g0
-    CHK(axpby(h, cplx(-1.0), h->d_G.p, cplx(1.0), h->d_tmp.p));  // tmp = T G + h - G
-    const double tr = norm(h, h->d_tmp.p);
-    h->st.true_rel_residual = hnorm > 0.0 ? tr / hnorm : 0.0;
+    double rel = 0.0;
+    CHK(residual_sweep(h, with_f, h->opt.precision, h->opt.tau_in, hnorm, &rel));
+    h->st.true_rel_residual = rel;
     h->has_state = true;
     return DD_OK;
 }
@@ -522,10 +598,14 @@ int check_finite(const double* x, int64_t n, const char* name) {
 
 int stage_source(dd_handle* h, const double* d_fre, const double* d_fim) {
     const int64_t n = h->L * h->nloc;
-    const size_t rs = real_size(h);
-    char* F = h->d_F.p;
-    HIPCHK(wdd::gather_source(d_fre, d_fim, h->d_gidx.p, h->d_area.p, n, F, F + rs * n,
-                              h->opt.precision == DD_FP32, h->stream));
+    for (int prec : {DD_FP64, DD_FP32}) {
+        const dd_handle::PrecBuf& B = h->pb[prec_index(prec)];
+        if (!B.present) continue;
+        const size_t rs = prec_size(prec);
+        char* F = B.F.p;
+        HIPCHK(wdd::gather_source(d_fre, d_fim, h->d_gidx.p, h->d_area.p, n, F, F + rs * n,
+                                  prec == DD_FP32, h->stream));
+    }
     return DD_OK;
 }
 
@@ -580,6 +660,7 @@ int dd_default_options(dd_options* o) {
     o->restart = 50;
     o->nt_override = 0;
     o->cfl = 0.9;
+    o->refine = 4;
     return DD_OK;
 }
 
@@ -587,7 +668,13 @@ void dd_destroy(dd_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->dev);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    h->d_desc.free(); h->d_coef.free(); h->d_tab.free(); h->d_F.free();
+    h->d_desc.free();
+    for (auto& B : h->pb) {
+        B.coef.free();
+        B.tab.free();
+        B.F.free();
+    }
+    h->d_D.free(); h->d_res.free();
     h->d_w1d.free(); h->d_kside.free(); h->d_area.free();
     h->d_gidx.free(); h->d_iters.free(); h->d_is_iface.free(); h->d_trace_idx.free();
     h->d_u.free(); h->d_V.free(); h->d_G.free(); h->d_h.free(); h->d_tmp.free(); h->d_g0.free();
@@ -631,6 +718,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(DD_EINVAL, "cfl must be in (0, 1]");
     if (o.nt_override < 0 || o.nt_override == 1 || o.nt_override == 2)
         return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
+    if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
     const int P = degree;
     const int Nx = mesh->nx * P + 1, Ny = mesh->ny * P + 1;
     const int64_t N = (int64_t)Nx * Ny;
@@ -849,9 +937,17 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     SCHK(hipEventCreate(&h->ev1));
     const size_t rs = real_size(h);
     SCHK(h->d_desc.alloc(L));
-    SCHK(h->d_coef.alloc(4 * rs * nn));
-    SCHK(h->d_tab.alloc(4 * rs * h->tab_len));
-    SCHK(h->d_F.alloc(2 * rs * nn));
+    h->pb[0].present = true;
+    h->pb[1].present = o.precision == DD_FP32;
+    for (auto& B : h->pb) {
+        if (!B.present) continue;
+        const size_t bs = (&B == &h->pb[1]) ? 4 : 8;
+        SCHK(B.coef.alloc(4 * bs * nn));
+        SCHK(B.tab.alloc(4 * bs * h->tab_len));
+        SCHK(B.F.alloc(2 * bs * nn));
+    }
+    SCHK(h->d_D.alloc(h->n_if));
+    SCHK(h->d_res.alloc(h->n_if));
     SCHK(h->d_w1d.alloc(nxl + nyl));
     SCHK(h->d_kside.alloc(h->n_if));
     SCHK(h->d_area.alloc(nn));
@@ -875,20 +971,25 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     SCHK(wdd::blas_init(h->blas, o.restart + 2, h->stream));
     h->iters_host.assign(L, 0);
 
-    auto up_real = [&](char* dst, const std::vector<double>& v) -> hipError_t {
-        if (rs == 8) return hipMemcpy(dst, v.data(), 8 * v.size(), hipMemcpyHostToDevice);
+    auto up_real = [&](char* dst, const std::vector<double>& v, size_t bs) -> hipError_t {
+        if (bs == 8) return hipMemcpy(dst, v.data(), 8 * v.size(), hipMemcpyHostToDevice);
         std::vector<float> f(v.begin(), v.end());
         return hipMemcpy(dst, f.data(), 4 * f.size(), hipMemcpyHostToDevice);
     };
     SCHK(hipMemcpy(h->d_desc.p, h->desc.data(), sizeof(wdd::SubDesc) * L, hipMemcpyHostToDevice));
-    SCHK(up_real(h->d_coef.p, alpha));
-    SCHK(up_real(h->d_coef.p + rs * nn, betaX));
-    SCHK(up_real(h->d_coef.p + 2 * rs * nn, betaY));
-    SCHK(up_real(h->d_coef.p + 3 * rs * nn, beta));
-    SCHK(up_real(h->d_tab.p, kap));
-    SCHK(up_real(h->d_tab.p + rs * h->tab_len, kaph));
-    SCHK(up_real(h->d_tab.p + 2 * rs * h->tab_len, cs));
-    SCHK(up_real(h->d_tab.p + 3 * rs * h->tab_len, sn));
+    for (auto& B : h->pb) {
+        if (!B.present) continue;
+        const size_t bs = (&B == &h->pb[1]) ? 4 : 8;
+        SCHK(up_real(B.coef.p, alpha, bs));
+        SCHK(up_real(B.coef.p + bs * nn, betaX, bs));
+        SCHK(up_real(B.coef.p + 2 * bs * nn, betaY, bs));
+        SCHK(up_real(B.coef.p + 3 * bs * nn, beta, bs));
+        SCHK(up_real(B.tab.p, kap, bs));
+        SCHK(up_real(B.tab.p + bs * h->tab_len, kaph, bs));
+        SCHK(up_real(B.tab.p + 2 * bs * h->tab_len, cs, bs));
+        SCHK(up_real(B.tab.p + 3 * bs * h->tab_len, sn, bs));
+        SCHK(hipMemset(B.F.p, 0, 2 * bs * nn));
+    }
     SCHK(hipMemcpy(h->d_w1d.p, w1d.data(), 8 * w1d.size(), hipMemcpyHostToDevice));
     SCHK(hipMemcpy(h->d_kside.p, kside.data(), 8 * kside.size(), hipMemcpyHostToDevice));
     SCHK(hipMemcpy(h->d_area.p, area.data(), 8 * area.size(), hipMemcpyHostToDevice));
@@ -899,7 +1000,6 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     SCHK(hipMemcpy(h->d_wyg.p, wyg.data(), 8 * (size_t)Ny, hipMemcpyHostToDevice));
     SCHK(hipMemcpy(h->d_Mg.p, Mg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
     SCHK(hipMemcpy(h->d_Hg.p, Hg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
-    SCHK(hipMemset(h->d_F.p, 0, 2 * rs * nn));
     SCHK(hipMemset(h->d_u.p, 0, sizeof(double2) * nn));
     SCHK(hipMemset(h->d_G.p, 0, sizeof(double2) * h->n_if));
     SCHK(hipMemset(h->d_g0.p, 0, sizeof(double2) * h->n_if));
@@ -1095,12 +1195,12 @@ int dd_apply_stiffness(dd_handle* h, const double* p, double* q) {
     }
     if (e == hipSuccess) {
         if (rs == 8) {
-            auto a = make_args<double>(h, h->d_g0.p, h->d_tmp.p, 0.0, false);
+            auto a = make_args<double>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
             e = h->layout == DD_LAYOUT_NODE
                     ? wdd::launch_apply_node<double>(a, h->P, h->wg, (double*)dp.p, (double*)dq.p, h->stream)
                     : wdd::launch_apply_patch<double>(a, h->P, h->wg, (double*)dp.p, (double*)dq.p, h->stream);
         } else {
-            auto a = make_args<float>(h, h->d_g0.p, h->d_tmp.p, 0.0, false);
+            auto a = make_args<float>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
             e = h->layout == DD_LAYOUT_NODE
                     ? wdd::launch_apply_node<float>(a, h->P, h->wg, (float*)dp.p, (float*)dq.p, h->stream)
                     : wdd::launch_apply_patch<float>(a, h->P, h->wg, (float*)dp.p, (float*)dq.p, h->stream);

@@ -41,7 +41,7 @@ class dd_partition(C.Structure):
 class dd_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("layout", C.c_int), ("tau_in", C.c_double),
                 ("max_wh", C.c_int), ("outer", C.c_int), ("restart", C.c_int),
-                ("nt_override", C.c_int), ("cfl", C.c_double)]
+                ("nt_override", C.c_int), ("cfl", C.c_double), ("refine", C.c_int)]
 
 
 class dd_stats(C.Structure):
@@ -49,7 +49,7 @@ class dd_stats(C.Structure):
                 ("true_rel_residual", C.c_double), ("wh_iters_total", C.c_int64),
                 ("wh_iters_max", C.c_int), ("nt_min", C.c_int), ("nt_max", C.c_int),
                 ("dof_updates", C.c_double), ("sweep_seconds", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("refine_steps", C.c_int), ("fp64_sweeps", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

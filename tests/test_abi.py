@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = wavedd.dd_default_options()
     assert o.precision == wavedd.DD_FP64 and o.restart == 50 and o.max_wh == 100
-    assert abs(o.cfl - 0.9) < 1e-15 and abs(o.tau_in - 1e-12) < 1e-27
+    assert abs(o.cfl - 0.9) < 1e-15 and abs(o.tau_in - 1e-12) < 1e-27 and o.refine == 4
 
 
 def _setup_rc(nx=4, ny=4, P=2, c=None, omega=3.0, sx=2, sy=2, **kw):
@@ -70,7 +70,7 @@ def test_setup_rejects_nonpositive_wavespeed():
 
 def test_setup_rejects_bad_options():
     for kw in (dict(precision=7), dict(restart=0), dict(cfl=1.5), dict(max_wh=0),
-               dict(nt_override=2), dict(layout=9), dict(outer=3)):
+               dict(nt_override=2), dict(layout=9), dict(outer=3), dict(refine=-1)):
         o = wavedd.dd_default_options(**kw)
         rc, _ = _setup_rc(options=o)
         assert rc == wavedd.DD_EINVAL, kw

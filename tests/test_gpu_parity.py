@@ -185,15 +185,31 @@ def test_solve_c1_tight_matches_global_lu(gpu_lib):
     assert rel_res < 1e-10
 
 
-def test_solve_c1_fp32_inner(gpu_lib):
+def test_solve_c1_fp32_refined(gpu_lib):
+    """FP32 sweeps with FP64 residual refinement reach the FP64 answer."""
     W = gpu_lib
-    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-7)
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-6)
+    u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol)
+    W.dd_destroy(h)
+    u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
+    err = _rel([u], [u_lu])
+    print(f"c1 fp32+refine err={err:.3e} iters={st['outer_iters']} refine={st['refine_steps']} "
+          f"true_res={st['true_rel_residual']:.2e}")
+    assert st["true_rel_residual"] <= wl.tol
+    assert err < 1e-6
+
+
+def test_solve_c1_fp32_plain(gpu_lib):
+    """FP32 sweeps and FP32-accurate outer residuals only: the error floor is
+    the FP32 operator's (reported, bounded loosely)."""
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-6, refine=0)
     u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, allow_notconv=True)
     W.dd_destroy(h)
     u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
     err = _rel([u], [u_lu])
-    print(f"c1 fp32 err={err:.3e} iters={st['outer_iters']} true_res={st['true_rel_residual']:.2e}")
-    assert err < 1e-6
+    print(f"c1 fp32 plain err={err:.3e} true_res={st['true_rel_residual']:.2e}")
+    assert err < 1e-4
 
 
 def test_plane_wave_boundary_data(gpu_lib):
