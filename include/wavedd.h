@@ -64,9 +64,10 @@ extern "C" {
 #define DD_FP64 0          /* subdomain sweep in double precision */
 #define DD_FP32 1          /* subdomain sweep in single precision, outer FP64 */
 
-#define DD_LAYOUT_AUTO 0   /* pick by measurement (autotuner) */
-#define DD_LAYOUT_NODE 1   /* one DOF per thread, state in registers + LDS */
-#define DD_LAYOUT_PATCH 2  /* one element patch (P*P DOFs) per thread */
+#define DD_LAYOUT_AUTO 0        /* pick by measurement (autotuner) */
+#define DD_LAYOUT_NODE 1        /* one DOF per thread, state in registers + LDS */
+#define DD_LAYOUT_PATCH 2       /* one element patch (P*P DOFs) per thread, one barrier/step */
+#define DD_LAYOUT_PATCH_XCHG 3  /* same ownership, partial-sum exchange, two barriers/step */
 
 #define DD_OUTER_GMRES 0
 #define DD_OUTER_FIXED 1

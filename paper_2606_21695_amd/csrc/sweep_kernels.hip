@@ -10,8 +10,8 @@
 // Khat the assembled reference 1D stiffness (element blocks D^T W D).  The
 // weights are folded with beta into per-node coefficients betaX, betaY.
 //
-// Two layouts:
-//  * PATCH: thread t = ey*mx + ex owns the P*P nodes (ex*P+a, ey*P+b),
+// Layouts:
+//  * PATCH_XCHG: thread t = ey*mx + ex owns the P*P nodes (ex*P+a, ey*P+b),
 //    a,b < P, of element (ex, ey), in registers; the subdomain's right
 //    column and top row of nodes (mx*P + my*P + 1 of them) are an extra
 //    one-node "edge" slot on the first threads.  Only element-boundary values
@@ -19,6 +19,9 @@
 //    reads its right neighbour's column and top neighbour's row, and exchanges
 //    partial sums for the shared vertex lines (two workgroup barriers per
 //    step).  Interior slots finish between the two barriers.
+//  * PATCH (default): the same ownership with one barrier per step: whole
+//    patches are published (double-buffered) and each thread computes its
+//    left / bottom neighbours' shares of its vertex lines itself.
 //  * NODE: one thread per node (<= 1024 nodes); p double-buffered in LDS
 //    with zero padding, so the (2P+1)-point 1D windows need no bounds
 //    checks (one barrier per step).
@@ -250,7 +253,7 @@ __device__ __forceinline__ void window_coeffs(Real (&w)[2 * P + 1], int k, int n
 // (right column) and GR (top row) carry kMaxP zeros on both ends so their
 // windows need no bounds checks.
 struct PatchLds {
-    int vc, vr, sx, sy, gc, gr, zr, corner, kl, tab, total;
+    int vc, vr, sx, sy, gc, gr, zr, corner, sink, kl, tab, total;
 };
 
 __host__ __device__ inline PatchLds patch_lds(int mx, int my, int P, int nt_max) {
@@ -263,8 +266,9 @@ __host__ __device__ inline PatchLds patch_lds(int mx, int my, int P, int nt_max)
     L.gc = L.sy + np;
     L.gr = L.gc + my * P + 1 + 2 * kMaxP;
     L.zr = L.gr + mx * P + 1 + 2 * kMaxP;
-    L.corner = L.zr + kMaxP;
-    L.kl = L.corner + 2;
+    L.corner = L.zr + 2 * kMaxP + 2;
+    L.sink = L.corner + 2;
+    L.kl = L.sink + 2 * kMaxP;
     L.tab = L.kl + (kMaxP + 1) * (kMaxP + 1);
     L.tab = (L.tab + 3) & ~3;  // 4-aligned quadruples
     L.total = L.tab + 4 * nt_max;
@@ -290,6 +294,7 @@ struct PatchCtx {
     int ex, ey;
     Real* VC; Real* VR; Real* SX; Real* SY; Real* GC; Real* GR; Real* CORN; const Real* TAB;
     const Real* pR; const Real* pT; const Real* pL; const Real* pB;
+    Real* wVC; Real* wVR; Real* wSX; Real* wSY;  // own publish targets (a sink without a patch)
     // edge slot
     bool e_col, e_corner, e_wcorner;
     int ek, e_il, e_jl;
@@ -327,13 +332,23 @@ struct PatchCtx {
         pT = (ey + 1 < my) ? VR + (t + mx) * P : GR + ex * P;
         pL = (ex > 0) ? SX + (t - 1) * P : ZR;
         pB = (ey > 0) ? SY + (t - mx) * P : ZR;
+        Real* SINK = lds + L.sink;
+        wVC = hasP ? VC + tid * P : SINK;
+        wVR = hasP ? VR + tid * P : SINK;
+        wSX = hasP ? SX + tid * P : SINK;
+        wSY = hasP ? SY + tid * P : SINK;
         const int mxP = mx * P, myP = my * P;
         hasE = tid < mxP + myP + 1;
         e_col = tid <= myP;
         ek = hasE ? (e_col ? tid : tid - (myP + 1)) : 0;
         e_corner = hasE && e_col && ek == myP;
         e_wcorner = hasE && !e_col && ek == (mx - 1) * P;
-        if (e_col) {
+        if (!hasE) {
+            e_il = e_jl = 0;
+            e_pub = SINK + kMaxP;
+            e_line = ZR + P;        // reads ZR[0..2P] (zeros; never written)
+            e_perp = ZR;
+        } else if (e_col) {
             e_il = mxP;
             e_jl = ek;
             e_pub = GC + ek;
@@ -363,17 +378,12 @@ struct PatchCtx {
     // Publish the values other threads need: the a=0 column and b=0 row of
     // the patch, and the edge node (the corner is stored in both lines).
     __device__ __forceinline__ void publish(const Real (&p)[P][P], Real ep, int mx) {
-        if (hasP) {
-            const int t = threadIdx.x;
 #pragma unroll
-            for (int b = 0; b < P; ++b) VC[t * P + b] = p[0][b];
+        for (int b = 0; b < P; ++b) wVC[b] = p[0][b];
 #pragma unroll
-            for (int a = 0; a < P; ++a) VR[t * P + a] = p[a][0];
-        }
-        if (hasE) {
-            *e_pub = ep;
-            if (e_corner) GR[mx * P] = ep;
-        }
+        for (int a = 0; a < P; ++a) wVR[a] = p[a][0];
+        *e_pub = ep;
+        if (e_corner) GR[mx * P] = ep;
     }
 
     // x-sum at (a, b) of this element (right vertex value pr = p(P, b)).
@@ -485,75 +495,122 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
         for (int nu = 1; nu < nt; ++nu) {
             const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
             const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
-            // p^{nu} = p^{nu-1} + sigma pdot^{nu-1/2}
+            // p^{nu} = p^{nu-1} + sigma pdot^{nu-1/2}; publish the vertex lines
 #pragma unroll
             for (int a = 0; a < P; ++a)
 #pragma unroll
                 for (int b = 0; b < P; ++b) p[a][b] = fma(sig, pd[a][b], p[a][b]);
             e.p = fma(sig, e.pd, e.p);
             C.publish(p, e.p, mx);
+            // own-data work while the writes drain: filter sum and forcing
+            Real tv[P][P];
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    vr[a][b] = fma(k1, p[a][b], vr[a][b]);
+                    if (vline<P>(a, b) || HAS_SRC)
+                        tv[a][b] = fma(cf.bbi[a][b], sv, cf.bbr[a][b] * c);
+                    else
+                        tv[a][b] = Real(0);
+                }
+            e.vr = fma(k1, e.p, e.vr);
             __syncthreads();
 
-            // pending velocity increments of the vertex-line slots
-            Real tv[P][P];
-            if (C.hasP) {
-                Real pr[P], pt[P];
+            // neighbour reads first; own-element sums hide their latency, the
+            // neighbour term is added last in every sum
+            Real pr[P], pt[P], ew[2 * P + 1];
 #pragma unroll
-                for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
+            for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
 #pragma unroll
-                for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
-                // partial sums owed to the right / top neighbours' vertex lines
+            for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
 #pragma unroll
-                for (int b = 0; b < P; ++b) C.SX[threadIdx.x * P + b] = C.xsum(p, P, b, pr[b]);
+            for (int j = 0; j <= 2 * P; ++j) ew[j] = C.e_line[j - P];
+            Real X[P][P], Y[P][P], sx[P], sy[P];
 #pragma unroll
-                for (int a = 0; a < P; ++a) C.SY[threadIdx.x * P + a] = C.ysum(p, a, P, pt[a]);
+            for (int b = 0; b < P; ++b) {
+                sx[b] = C.K(P, 0) * p[0][b];
+#pragma unroll
+                for (int q = 1; q < P; ++q) sx[b] = fma(C.K(P, q), p[q][b], sx[b]);
+            }
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+                sy[a] = C.K(P, 0) * p[a][0];
+#pragma unroll
+                for (int q = 1; q < P; ++q) sy[a] = fma(C.K(P, q), p[a][q], sy[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    X[a][b] = C.K(a, 0) * p[0][b];
+#pragma unroll
+                    for (int q = 1; q < P; ++q) X[a][b] = fma(C.K(a, q), p[q][b], X[a][b]);
+                    Y[a][b] = C.K(b, 0) * p[a][0];
+#pragma unroll
+                    for (int q = 1; q < P; ++q) Y[a][b] = fma(C.K(b, q), p[a][q], Y[a][b]);
+                }
+            // partial sums owed to the right / top neighbours' vertex lines
+#pragma unroll
+            for (int b = 0; b < P; ++b) C.wSX[b] = fma(C.K(P, P), pr[b], sx[b]);
+#pragma unroll
+            for (int a = 0; a < P; ++a) C.wSY[a] = fma(C.K(P, P), pt[a], sy[a]);
+            Real eL = Real(0);
+#pragma unroll
+            for (int j = 0; j <= 2 * P; ++j) eL = fma(C.ew[j], ew[j], eL);
+            if (C.e_wcorner) {
+                Real cc = Real(0);
+#pragma unroll
+                for (int q = 0; q <= P; ++q) cc = fma(C.K(P, q), ew[P + q], cc);
+                *C.CORN = cc;
+            }
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    const Real Xf = fma(C.K(a, P), pr[b], X[a][b]);
+                    const Real Yf = fma(C.K(b, P), pt[a], Y[a][b]);
+                    Real t = fma(-cf.bX[a][b], Xf, tv[a][b]);
+                    t = fma(-cf.bY[a][b], Yf, t);
+                    if (vline<P>(a, b))
+                        tv[a][b] = t;  // finished after the partials arrive
+                    else
+                        pd[a][b] += t;
+                }
+            __syncthreads();
+            {
+                Real pl[P], pbm[P];
+#pragma unroll
+                for (int b = 0; b < P; ++b) pl[b] = C.pL[b];
+#pragma unroll
+                for (int a = 0; a < P; ++a) pbm[a] = C.pB[a];
+                const Real eP = *C.e_perp;
+                // interior slots: filter sum of the new velocity
 #pragma unroll
                 for (int a = 0; a < P; ++a)
 #pragma unroll
-                    for (int b = 0; b < P; ++b) {
-                        const Real X = C.xsum(p, a, b, pr[b]);
-                        const Real Y = C.ysum(p, a, b, pt[a]);
-                        Real t;
-                        if (vline<P>(a, b) || HAS_SRC) {
-                            t = cf.bbr[a][b] * c;
-                            t = fma(cf.bbi[a][b], sv, t);
-                            t = fma(-cf.bX[a][b], X, t);
-                        } else {
-                            t = -cf.bX[a][b] * X;
-                        }
-                        t = fma(-cf.bY[a][b], Y, t);
-                        if (vline<P>(a, b)) {
-                            tv[a][b] = t;  // finished after the partials arrive
-                        } else {
-                            pd[a][b] += t;
-                            vr[a][b] = fma(k1, p[a][b], vr[a][b]);
-                            vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
-                        }
-                    }
-            }
-            Real eL = Real(0);
-            if (C.hasE) eL = C.edge_line_sum();
-            __syncthreads();
-            if (C.hasP) {
+                    for (int b = 0; b < P; ++b)
+                        if (!vline<P>(a, b)) vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
 #pragma unroll
-                for (int b = 0; b < P; ++b) tv[0][b] = fma(-cf.bX[0][b], C.pL[b], tv[0][b]);
+                for (int b = 0; b < P; ++b) tv[0][b] = fma(-cf.bX[0][b], pl[b], tv[0][b]);
 #pragma unroll
-                for (int a = 0; a < P; ++a) tv[a][0] = fma(-cf.bY[a][0], C.pB[a], tv[a][0]);
+                for (int a = 1; a < P; ++a) tv[a][0] = fma(-cf.bY[a][0], pbm[a], tv[a][0]);
+                tv[0][0] = fma(-cf.bY[0][0], pbm[0], tv[0][0]);
 #pragma unroll
                 for (int a = 0; a < P; ++a)
 #pragma unroll
                     for (int b = 0; b < P; ++b)
                         if (vline<P>(a, b)) {
                             pd[a][b] = fma(cf.al[a][b], pd[a][b], tv[a][b]);
-                            vr[a][b] = fma(k1, p[a][b], vr[a][b]);
                             vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
                         }
-            }
-            if (C.hasE) {
-                const Real eP = *C.e_perp;
                 const Real eX = C.e_col ? eP : eL;
                 const Real eY = C.e_col ? eL : eP;
-                slot_step(e, eX, eY, c, sv, k1, k2);
+                Real t = fma(e.bbi, sv, e.bbr * c);
+                t = fma(-e.bX, eX, t);
+                t = fma(-e.bY, eY, t);
+                e.pd = fma(e.al, e.pd, t);
+                e.vi = fma(k2, e.pd, e.vi);
             }
         }
 
@@ -666,6 +723,438 @@ __global__ void __launch_bounds__(WG) apply_patch_kernel(const SweepArgs<Real> A
         const Real eP = *C.e_perp;
         const Real eX = C.e_col ? eP : eL;
         const Real eY = C.e_col ? eL : eP;
+        qout[d.node_off + (int64_t)C.e_jl * nxl + C.e_il] =
+            (Real)(d.sx_ref * wy[C.e_jl]) * eX + (Real)(d.sy_ref * wx[C.e_il]) * eY;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// PATCH layout, one barrier per step
+// ---------------------------------------------------------------------------
+// Same ownership as above, but every thread publishes its whole P*P patch
+// (structure-of-arrays, double-buffered by step parity) and computes the
+// contributions of its left and bottom neighbour elements to its own vertex
+// lines itself, so a step needs one barrier and one LDS round trip.  The hot
+// loop is branch-free: missing neighbours read a zero column, threads without
+// a patch or an edge node publish into unused columns / a sink.
+//
+// LDS (units of Real): PB[2][P*P][S] with S = WG + 64 (column WG..S-1 is a
+// zero column, so S is a multiple of 64), GC[2][myP+1+2kMaxP],
+// GR[2][mxP+1+2kMaxP], zero line, sink, K, tables.
+struct Patch1Lds {
+    int pb, gc, gr, zr, sink, kl, tab, total, S, lgc, lgr;
+};
+
+__host__ __device__ inline Patch1Lds patch1_lds(int mx, int my, int P, int WG, int nt_max) {
+    Patch1Lds L;
+    L.S = WG + 64;
+    L.lgc = my * P + 1 + 2 * kMaxP;
+    L.lgr = mx * P + 1 + 2 * kMaxP;
+    L.pb = 0;
+    L.gc = L.pb + 2 * P * P * L.S;
+    L.gr = L.gc + 2 * L.lgc;
+    L.zr = L.gr + 2 * L.lgr;
+    L.sink = L.zr + 2 * kMaxP + 2;
+    L.kl = L.sink + 2;
+    L.tab = (L.kl + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
+    L.total = L.tab + 4 * nt_max;
+    return L;
+}
+
+// Per-thread addressing of the one-barrier patch layout.  Every neighbour
+// read is base[k * stride] in buffer (nu & 1), whose offset from buffer 0 is
+// `boff` (the two buffers of PB and of each line differ in size).
+template <typename Real, int P, int WG>
+struct Patch1Ctx {
+    Real* lds;
+    int own;                        // own PB column
+    int rB, rS, rO;                 // right neighbour's a=0 column: base, stride, buffer offset
+    int tB, tS, tO;                 // top neighbour's b=0 row
+    int lB, bB;                     // left / bottom neighbour PB columns (zero column if absent)
+    Real kl, kb;                    // K[P][P] if the left / bottom element exists, else 0
+    bool hasP, hasE, e_col, e_corner;
+    int ek, e_il, e_jl;
+    int pubB, pubO, pub2B, pub2O;   // edge publish (and corner copy into GR; sink otherwise)
+    int lnB, lnO;                   // edge: own line (centre)
+    int ppB, ppS, ppO;              // edge: perpendicular reads
+    Real ew[2 * P + 1];
+    const double (*K1)[kMaxP + 1];
+
+    __device__ __forceinline__ Real K(int a, int b) const {
+        return (Real)K1[kcan_a<P>(a, b)][kcan_b<P>(a, b)];
+    }
+
+    __device__ void setup(const SubDesc& d, Real* lds_, const double (*K1_)[kMaxP + 1],
+                          int nt_max) {
+        lds = lds_;
+        K1 = K1_;
+        const int mx = d.mx, my = d.my, tid = threadIdx.x;
+        const Patch1Lds L = patch1_lds(mx, my, P, WG, nt_max);
+        const int S = L.S, pbO = P * P * S;
+        // zero both PB buffers' zero columns, the lines, the zero line
+        for (int i = tid; i < 2 * P * P * 64; i += blockDim.x) {
+            const int buf = i / (P * P * 64), r = i % (P * P * 64);
+            lds[L.pb + buf * pbO + (r / 64) * S + WG + (r % 64)] = Real(0);
+        }
+        for (int i = L.gc + tid; i < L.kl; i += blockDim.x) lds[i] = Real(0);
+        if (tid < (P + 1) * (P + 1)) lds[L.kl + tid] = (Real)K1[tid / (P + 1)][tid % (P + 1)];
+        const int np = mx * my;
+        hasP = tid < np;
+        const int ex = hasP ? tid % mx : 0, ey = hasP ? tid / mx : 0;
+        own = L.pb + tid;
+        const int zc = L.pb + WG;   // zero column
+        if (hasP && ex + 1 < mx) { rB = L.pb + tid + 1; rS = S; rO = pbO; }
+        else if (hasP) { rB = L.gc + kMaxP + ey * P; rS = 1; rO = L.lgc; }
+        else { rB = zc; rS = S; rO = pbO; }
+        if (hasP && ey + 1 < my) { tB = L.pb + tid + mx; tS = P * S; tO = pbO; }
+        else if (hasP) { tB = L.gr + kMaxP + ex * P; tS = 1; tO = L.lgr; }
+        else { tB = zc; tS = P * S; tO = pbO; }
+        lB = (hasP && ex > 0) ? L.pb + tid - 1 : zc;
+        bB = (hasP && ey > 0) ? L.pb + tid - mx : zc;
+        kl = (hasP && ex > 0) ? K(P, P) : Real(0);
+        kb = (hasP && ey > 0) ? K(P, P) : Real(0);
+        // edge slot
+        const int mxP = mx * P, myP = my * P;
+        hasE = tid < mxP + myP + 1;
+        e_col = tid <= myP;
+        ek = hasE ? (e_col ? tid : tid - (myP + 1)) : 0;
+        e_corner = hasE && e_col && ek == myP;
+        pub2B = L.sink;
+        pub2O = 0;
+        if (!hasE) {
+            e_il = e_jl = 0;
+            pubB = L.sink; pubO = 0;
+            lnB = L.zr + kMaxP; lnO = 0;
+            ppB = L.zr; ppS = 0; ppO = 0;
+        } else if (e_col) {
+            e_il = mxP;
+            e_jl = ek;
+            pubB = L.gc + kMaxP + ek; pubO = L.lgc;
+            if (e_corner) {
+                pub2B = L.gr + kMaxP + mxP;
+                pub2O = L.lgr;
+            }
+            lnB = L.gc + kMaxP + ek; lnO = L.lgc;
+            if (e_corner) {
+                ppB = L.gr + kMaxP + (mx - 1) * P; ppS = 1; ppO = L.lgr;
+            } else {
+                const int eyk = ek / P, b = ek - eyk * P;
+                ppB = L.pb + b * S + eyk * mx + (mx - 1); ppS = P * S; ppO = pbO;
+            }
+        } else {
+            e_il = ek;
+            e_jl = myP;
+            pubB = L.gr + kMaxP + ek; pubO = L.lgr;
+            lnB = L.gr + kMaxP + ek; lnO = L.lgr;
+            const int exk = ek / P, a = ek - exk * P;
+            ppB = L.pb + (a * P) * S + (my - 1) * mx + exk; ppS = S; ppO = pbO;
+        }
+    }
+
+    __device__ void setup_windows(const SubDesc& d, int nt_max) {
+        const Patch1Lds L = patch1_lds(d.mx, d.my, P, WG, nt_max);
+        window_coeffs<Real, P>(ew, ek, e_col ? d.my : d.mx, lds + L.kl);
+        if (!hasE) {
+#pragma unroll
+            for (int j = 0; j <= 2 * P; ++j) ew[j] = Real(0);
+        }
+    }
+};
+
+template <typename Real, int P, int WG, bool HAS_SRC>
+__device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
+                                  double* red) {
+    Patch1Ctx<Real, P, WG> C;
+    C.setup(d, lds, A.K1[P], A.nt_max);
+    const Patch1Lds LL = patch1_lds(d.mx, d.my, P, WG, A.nt_max);
+    const int S = LL.S, pbO = P * P * S;
+    stage_tables(A, d, lds + LL.tab);
+    const int nxl = d.nxl;
+    PatchCoef<Real, P, HAS_SRC> cf;
+    Real p[P][P], pd[P][P], vr[P][P], vi[P][P];
+    const int ex = C.hasP ? threadIdx.x % d.mx : 0, ey = C.hasP ? threadIdx.x / d.mx : 0;
+    const int64_t base = d.node_off + (int64_t)(ey * P) * nxl + ex * P;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            cf.bX[a][b] = cf.bY[a][b] = cf.al[a][b] = cf.bbr[a][b] = cf.bbi[a][b] = Real(0);
+            p[a][b] = pd[a][b] = vr[a][b] = vi[a][b] = Real(0);
+            if (C.hasP) {
+                const int64_t n = base + (int64_t)b * nxl + a;
+                cf.bX[a][b] = A.coef.betaX[n];
+                cf.bY[a][b] = A.coef.betaY[n];
+                if (vline<P>(a, b) || HAS_SRC) {
+                    const double be = (double)A.coef.beta[n];
+                    const double2 bb = assemble_b(A, d, ex * P + a, ey * P + b);
+                    cf.bbr[a][b] = (Real)(be * bb.x);
+                    cf.bbi[a][b] = (Real)(be * bb.y);
+                }
+                if (vline<P>(a, b)) cf.al[a][b] = A.coef.alpha[n];
+            }
+        }
+    Slot<Real> e;
+    slot_zero(e);
+    if (C.hasE) slot_load(e, A, d, C.e_il, C.e_jl);
+    __syncthreads();
+    C.setup_windows(d, A.nt_max);
+
+    const Real sig = (Real)d.sigma;
+    const int nt = d.nt;
+    const Real* TAB = lds + LL.tab;
+    const double pd0c = d.pd0c, pd0s = d.pd0s;
+    const Real kPP = C.K(P, P);
+    int it = 0;
+    for (int m = 0; m < A.max_wh; ++m) {
+        const Real k0 = TAB[2], kh0 = TAB[3];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                if (m > 0 && C.hasP) {
+                    const double2 u = A.u[base + (int64_t)b * nxl + a];
+                    p[a][b] = (Real)u.x;
+                    pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
+                } else {
+                    p[a][b] = Real(0);
+                    pd[a][b] = Real(0);
+                }
+                vr[a][b] = k0 * p[a][b];
+                vi[a][b] = kh0 * pd[a][b];
+            }
+        if (C.hasE) slot_init(e, A, d, m > 0, k0, kh0);
+
+        for (int nu = 1; nu < nt; ++nu) {
+            const int par = nu & 1;
+            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
+            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
+            // p^{nu} = p^{nu-1} + sigma pdot^{nu-1/2}; publish the patch
+            Real* pbuf = lds + C.own + par * pbO;
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    p[a][b] = fma(sig, pd[a][b], p[a][b]);
+                    pbuf[(a * P + b) * S] = p[a][b];
+                }
+            e.p = fma(sig, e.pd, e.p);
+            lds[C.pubB + par * C.pubO] = e.p;
+            lds[C.pub2B + par * C.pub2O] = e.p;
+            // own-data work while the writes drain: filter sum and forcing
+            Real tf[P][P];
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    vr[a][b] = fma(k1, p[a][b], vr[a][b]);
+                    if (vline<P>(a, b) || HAS_SRC)
+                        tf[a][b] = fma(cf.bbi[a][b], sv, cf.bbr[a][b] * c);
+                    else
+                        tf[a][b] = Real(0);
+                }
+            e.vr = fma(k1, e.p, e.vr);
+            __syncthreads();
+
+            // neighbour values (right column, top row, left and bottom patches)
+            Real pr[P], pt[P], pl[P][P], pb[P][P];
+            {
+                const Real* r = lds + C.rB + par * C.rO;
+                const Real* t = lds + C.tB + par * C.tO;
+                const Real* l = lds + C.lB + par * pbO;
+                const Real* bo = lds + C.bB + par * pbO;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    pr[q] = r[q * C.rS];
+                    pt[q] = t[q * C.tS];
+                }
+#pragma unroll
+                for (int a = 0; a < P; ++a)
+#pragma unroll
+                    for (int b = 0; b < P; ++b) {
+                        pl[a][b] = l[(a * P + b) * S];
+                        pb[a][b] = bo[(a * P + b) * S];
+                    }
+            }
+            Real ew[2 * P + 1], epp[P];
+            {
+                const Real* ln = lds + C.lnB + C.lnO * par;
+                const Real* pp = lds + C.ppB + C.ppO * par;
+#pragma unroll
+                for (int j = 0; j <= 2 * P; ++j) ew[j] = ln[j - P];
+#pragma unroll
+                for (int q = 0; q < P; ++q) epp[q] = pp[q * C.ppS];
+            }
+            // own-element terms first (they hide the LDS latency), neighbour
+            // terms last
+            Real X[P][P], Y[P][P];
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    X[a][b] = C.K(a, 0) * p[0][b];
+#pragma unroll
+                    for (int q = 1; q < P; ++q) X[a][b] = fma(C.K(a, q), p[q][b], X[a][b]);
+                    Y[a][b] = C.K(b, 0) * p[a][0];
+#pragma unroll
+                    for (int q = 1; q < P; ++q) Y[a][b] = fma(C.K(b, q), p[a][q], Y[a][b]);
+                    if (a == 0) X[a][b] = fma(C.kl, p[0][b], X[a][b]);
+                    if (b == 0) Y[a][b] = fma(C.kb, p[a][0], Y[a][b]);
+                }
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    Real Xf = fma(C.K(a, P), pr[b], X[a][b]);
+                    Real Yf = fma(C.K(b, P), pt[a], Y[a][b]);
+                    if (a == 0) {  // left element's share of this vertex-line node
+#pragma unroll
+                        for (int q = 0; q < P; ++q) Xf = fma(C.K(P, q), pl[q][b], Xf);
+                    }
+                    if (b == 0) {  // bottom element's share
+#pragma unroll
+                        for (int q = 0; q < P; ++q) Yf = fma(C.K(P, q), pb[a][q], Yf);
+                    }
+                    Real tt = fma(-cf.bX[a][b], Xf, tf[a][b]);
+                    tt = fma(-cf.bY[a][b], Yf, tt);
+                    if (vline<P>(a, b))
+                        pd[a][b] = fma(cf.al[a][b], pd[a][b], tt);
+                    else
+                        pd[a][b] += tt;
+                    vi[a][b] = fma(k2, pd[a][b], vi[a][b]);
+                }
+            // edge node: window on its own line, and the perpendicular element
+            {
+                Real sL = Real(0);
+#pragma unroll
+                for (int j = 0; j <= 2 * P; ++j) sL = fma(C.ew[j], ew[j], sL);
+                Real sP = kPP * e.p;
+#pragma unroll
+                for (int q = 0; q < P; ++q) sP = fma(C.K(P, q), epp[q], sP);
+                const Real eX = C.e_col ? sP : sL;
+                const Real eY = C.e_col ? sL : sP;
+                Real t = fma(e.bbi, sv, e.bbr * c);
+                t = fma(-e.bX, eX, t);
+                t = fma(-e.bY, eY, t);
+                e.pd = fma(e.al, e.pd, t);
+                e.vi = fma(k2, e.pd, e.vi);
+            }
+        }
+
+        double dsum = 0.0, nsum = 0.0;
+        if (C.hasP) {
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    const int64_t n = base + (int64_t)b * nxl + a;
+                    const double ur = d.two_over_nt * (double)vr[a][b];
+                    const double ui = d.two_over_nt * (double)vi[a][b];
+                    double orr = 0.0, oi = 0.0;
+                    if (m > 0) {
+                        const double2 o = A.u[n];
+                        orr = o.x;
+                        oi = o.y;
+                    }
+                    dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+                    nsum += ur * ur + ui * ui;
+                    A.u[n] = make_double2(ur, ui);
+                }
+        }
+        if (C.hasE) slot_finish(e, A, d, m > 0, dsum, nsum);
+        block_sum2(dsum, nsum, red);
+        it = m + 1;
+        if (!(dsum == dsum)) break;
+        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+    }
+    __threadfence_block();
+    __syncthreads();
+    exchange(A, d);
+    if (threadIdx.x == 0) A.wh_iters[item] = it;
+}
+
+template <typename Real, int P, int WG, bool HAS_SRC>
+__global__ void __launch_bounds__(WG) sweep_patch1_kernel(const SweepArgs<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const SubDesc d = A.desc[item];
+        sweep_patch1_item<Real, P, WG, HAS_SRC>(A, d, item, lds, red);
+        __syncthreads();
+    }
+}
+
+// q = A p with the one-barrier patch routines (test path).
+template <typename Real, int P, int WG>
+__global__ void __launch_bounds__(WG) apply_patch1_kernel(const SweepArgs<Real> A,
+                                                          const Real* pin, Real* qout) {
+    extern __shared__ double smem_d[];
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    const SubDesc d = A.desc[blockIdx.x];
+    Patch1Ctx<Real, P, WG> C;
+    C.setup(d, lds, A.K1[P], A.nt_max);
+    const Patch1Lds LL = patch1_lds(d.mx, d.my, P, WG, A.nt_max);
+    const int S = LL.S;
+    const int nxl = d.nxl;
+    const int ex = C.hasP ? threadIdx.x % d.mx : 0, ey = C.hasP ? threadIdx.x / d.mx : 0;
+    const int64_t base = d.node_off + (int64_t)(ey * P) * nxl + ex * P;
+    Real p[P][P];
+    Real ep = Real(0);
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) p[a][b] = C.hasP ? pin[base + (int64_t)b * nxl + a] : Real(0);
+    if (C.hasE) ep = pin[d.node_off + (int64_t)C.e_jl * nxl + C.e_il];
+    __syncthreads();
+    C.setup_windows(d, A.nt_max);
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) lds[C.own + (a * P + b) * S] = p[a][b];
+    lds[C.pubB] = ep;
+    lds[C.pub2B] = ep;
+    __syncthreads();
+    const double* wx = A.w1d + d.w_off;
+    const double* wy = wx + d.nxl;
+    const Real* r = lds + C.rB;
+    const Real* t = lds + C.tB;
+    const Real* l = lds + C.lB;
+    const Real* bo = lds + C.bB;
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            Real X = C.K(a, P) * r[b * C.rS];
+#pragma unroll
+            for (int q = 0; q < P; ++q) X = fma(C.K(a, q), p[q][b], X);
+            Real Y = C.K(b, P) * t[a * C.tS];
+#pragma unroll
+            for (int q = 0; q < P; ++q) Y = fma(C.K(b, q), p[a][q], Y);
+            if (a == 0) {
+                X = fma(C.kl, p[0][b], X);
+#pragma unroll
+                for (int q = 0; q < P; ++q) X = fma(C.K(P, q), l[(q * P + b) * S], X);
+            }
+            if (b == 0) {
+                Y = fma(C.kb, p[a][0], Y);
+#pragma unroll
+                for (int q = 0; q < P; ++q) Y = fma(C.K(P, q), bo[(a * P + q) * S], Y);
+            }
+            if (C.hasP) {
+                const int il = ex * P + a, jl = ey * P + b;
+                qout[base + (int64_t)b * nxl + a] =
+                    (Real)(d.sx_ref * wy[jl]) * X + (Real)(d.sy_ref * wx[il]) * Y;
+            }
+        }
+    if (C.hasE) {
+        Real sL = Real(0);
+#pragma unroll
+        for (int j = 0; j <= 2 * P; ++j) sL = fma(C.ew[j], lds[C.lnB + j - P], sL);
+        Real sP = C.K(P, P) * ep;
+#pragma unroll
+        for (int q = 0; q < P; ++q) sP = fma(C.K(P, q), lds[C.ppB + q * C.ppS], sP);
+        const Real eX = C.e_col ? sP : sL;
+        const Real eY = C.e_col ? sL : sP;
         qout[d.node_off + (int64_t)C.e_jl * nxl + C.e_il] =
             (Real)(d.sx_ref * wy[C.e_jl]) * eX + (Real)(d.sy_ref * wx[C.e_il]) * eY;
     }
@@ -806,6 +1295,13 @@ size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size) {
     return 40 * sizeof(double) + (size_t)patch_lds(mx, my, P, nt_max).total * real_size;
 }
 
+static inline int patch1_wg_bound(int wg) { return wg <= 256 ? 256 : 512; }
+
+size_t patch1_lds_bytes(int mx, int my, int P, int wg, int nt_max, size_t real_size) {
+    return 40 * sizeof(double) +
+           (size_t)patch1_lds(mx, my, P, patch1_wg_bound(wg), nt_max).total * real_size;
+}
+
 size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size) {
     return 40 * sizeof(double) + ((size_t)node_tab_off(nxl, nyl) + 4 * (size_t)nt_max) * real_size;
 }
@@ -837,6 +1333,47 @@ hipError_t launch_sweep_patch(const SweepArgs<Real>& a, int P, int wg, hipStream
 #undef L
 #undef L256
 #undef L512
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_sweep_patch1(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    const bool src = a.Fre != nullptr && a.src != 0.0;
+#define L(PP, W, S) \
+    hipLaunchKernelGGL((sweep_patch1_kernel<Real, PP, W, S>), dim3(a.n_items), dim3(wg), lds, s, a)
+#define L256(PP) if (src) L(PP, 256, true); else L(PP, 256, false)
+#define L512(PP) if (src) L(PP, 512, true); else L(PP, 512, false)
+    if (wg <= 256) {
+        WDD_DISPATCH_P(P, L256)
+    } else if (wg <= 512) {
+        WDD_DISPATCH_P(P, L512)
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef L
+#undef L256
+#undef L512
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_apply_patch1(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                               hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    if (wg <= 256) {
+#define L(PP) \
+    hipLaunchKernelGGL((apply_patch1_kernel<Real, PP, 256>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+        WDD_DISPATCH_P(P, L)
+#undef L
+    } else if (wg <= 512) {
+#define L(PP) \
+    hipLaunchKernelGGL((apply_patch1_kernel<Real, PP, 512>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+        WDD_DISPATCH_P(P, L)
+#undef L
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -882,6 +1419,12 @@ hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real
 
 template hipError_t launch_sweep_patch<double>(const SweepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_sweep_patch<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_sweep_patch1<double>(const SweepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_sweep_patch1<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_apply_patch1<double>(const SweepArgs<double>&, int, int, const double*,
+                                                double*, hipStream_t);
+template hipError_t launch_apply_patch1<float>(const SweepArgs<float>&, int, int, const float*,
+                                               float*, hipStream_t);
 template hipError_t launch_sweep_node<double>(const SweepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_sweep_node<float>(const SweepArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_apply_patch<double>(const SweepArgs<double>&, int, int, const double*,

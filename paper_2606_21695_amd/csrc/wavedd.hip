@@ -290,18 +290,21 @@ int patch_threads(const dd_handle* h) {
     return std::max(h->mx * h->my, h->mx * h->P + h->my * h->P + 1);
 }
 
+int layout_threads(const dd_handle* h, int layout) {
+    const int t = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl : patch_threads(h);
+    return ((t + 63) / 64) * 64;
+}
+
 size_t layout_lds(const dd_handle* h, int layout, int prec) {
     const size_t rs = prec_size(prec);
     if (layout == DD_LAYOUT_NODE) return wdd::node_lds_bytes(h->nxl, h->nyl, h->nt_max, rs);
-    return wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, rs);
+    if (layout == DD_LAYOUT_PATCH_XCHG) return wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, rs);
+    return wdd::patch1_lds_bytes(h->mx, h->my, h->P, layout_threads(h, layout), h->nt_max, rs);
 }
 
 void layout_config(dd_handle* h, int layout) {
     h->layout = layout;
-    if (layout == DD_LAYOUT_NODE)
-        h->wg = ((h->nxl * h->nyl + 63) / 64) * 64;
-    else
-        h->wg = ((patch_threads(h) + 63) / 64) * 64;
+    h->wg = layout_threads(h, layout);
     for (int prec : {DD_FP64, DD_FP32})
         h->pb[prec_index(prec)].lds_bytes = layout_lds(h, layout, prec);
 }
@@ -321,12 +324,14 @@ int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, boo
     hipError_t e;
     if (prec == DD_FP32) {
         auto a = make_args<float>(h, g_in, g_out, src, with_f, tau, max_wh);
-        e = h->layout == DD_LAYOUT_NODE ? wdd::launch_sweep_node<float>(a, h->P, h->wg, s)
-                                        : wdd::launch_sweep_patch<float>(a, h->P, h->wg, s);
+        e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_sweep_node<float>(a, h->P, h->wg, s)
+            : h->layout == DD_LAYOUT_PATCH ? wdd::launch_sweep_patch1<float>(a, h->P, h->wg, s)
+                                           : wdd::launch_sweep_patch<float>(a, h->P, h->wg, s);
     } else {
         auto a = make_args<double>(h, g_in, g_out, src, with_f, tau, max_wh);
-        e = h->layout == DD_LAYOUT_NODE ? wdd::launch_sweep_node<double>(a, h->P, h->wg, s)
-                                        : wdd::launch_sweep_patch<double>(a, h->P, h->wg, s);
+        e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_sweep_node<double>(a, h->P, h->wg, s)
+            : h->layout == DD_LAYOUT_PATCH ? wdd::launch_sweep_patch1<double>(a, h->P, h->wg, s)
+                                           : wdd::launch_sweep_patch<double>(a, h->P, h->wg, s);
     }
     HIPCHK(e);
     if (timed) HIPCHK(hipEventRecord(h->ev1, s));
@@ -641,6 +646,31 @@ wdd::OperatorArgs op_args(const dd_handle* h) {
     return a;
 }
 
+// Layout autotuner: time every layout that fits on this problem (two
+// fixed-count WaveHoltz iterations per subdomain, zero data: the kernels
+// have no data-dependent work) and keep the fastest.
+int autotune_layout(dd_handle* h) {
+    int best = h->layout;
+    double best_ms = 1e300;
+    for (int lay : {DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_NODE}) {
+        if (!layout_fits(h, lay)) continue;
+        layout_config(h, lay);
+        HIPCHK(hipMemsetAsync(h->d_g0.p, 0, sizeof(double2) * h->n_if, h->stream));
+        CHK(run_sweep(h, h->d_g0.p, h->d_tmp.p, 0.0, false, false, h->opt.precision, 0.0, 2));
+        reset_stats(h);
+        for (int r = 0; r < 3; ++r)
+            CHK(run_sweep(h, h->d_g0.p, h->d_tmp.p, 0.0, false, true, h->opt.precision, 0.0, 2));
+        const double ms = h->st.sweep_seconds;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = lay;
+        }
+    }
+    layout_config(h, best);
+    reset_stats(h);
+    return DD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -710,7 +740,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     else
         dd_default_options(&o);
     if (o.precision != DD_FP64 && o.precision != DD_FP32) return fail(DD_EINVAL, "bad precision");
-    if (o.layout < DD_LAYOUT_AUTO || o.layout > DD_LAYOUT_PATCH) return fail(DD_EINVAL, "bad layout");
+    if (o.layout < DD_LAYOUT_AUTO || o.layout > DD_LAYOUT_PATCH_XCHG) return fail(DD_EINVAL, "bad layout");
     if (o.max_wh < 1) return fail(DD_EINVAL, "max_wh must be >= 1");
     if (o.outer != DD_OUTER_GMRES && o.outer != DD_OUTER_FIXED)
         return fail(DD_EINVAL, "bad outer method");
@@ -789,19 +819,22 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
 
     // layout choice (validated before any device work)
     const bool node_ok = layout_fits(h, DD_LAYOUT_NODE), patch_ok = layout_fits(h, DD_LAYOUT_PATCH);
+    const bool xchg_ok = layout_fits(h, DD_LAYOUT_PATCH_XCHG);
     int lay = o.layout;
     const char* why = nullptr;
     if (lay == DD_LAYOUT_NODE && !node_ok)
         why = "one-DOF-per-thread layout needs <= 1024 nodes per subdomain";
     else if (lay == DD_LAYOUT_PATCH && !patch_ok)
+        why = "patch layout needs <= 512 threads (element patches) per subdomain and its LDS";
+    else if (lay == DD_LAYOUT_PATCH_XCHG && !xchg_ok)
         why = "patch layout needs <= 512 threads (element patches) per subdomain";
-    else if (!node_ok && !patch_ok)
+    else if (!node_ok && !patch_ok && !xchg_ok)
         why = "subdomain too large for the on-chip layouts";
     if (why) {
         delete h;
         return fail(DD_EINVAL, "%s (subdomain %dx%d elements, P=%d)", why, mx, my, P);
     }
-    if (lay == DD_LAYOUT_AUTO) lay = patch_ok ? DD_LAYOUT_PATCH : DD_LAYOUT_NODE;
+    if (lay == DD_LAYOUT_AUTO) lay = patch_ok ? DD_LAYOUT_PATCH : xchg_ok ? DD_LAYOUT_PATCH_XCHG : DD_LAYOUT_NODE;
     layout_config(h, lay);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1004,6 +1037,13 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     SCHK(hipMemset(h->d_G.p, 0, sizeof(double2) * h->n_if));
     SCHK(hipMemset(h->d_g0.p, 0, sizeof(double2) * h->n_if));
 #undef SCHK
+    if (o.layout == DD_LAYOUT_AUTO) {
+        const int rc = autotune_layout(h);
+        if (rc != DD_OK) {
+            dd_destroy(h);
+            return rc;
+        }
+    }
     *out = h;
     return DD_OK;
 }
@@ -1196,14 +1236,18 @@ int dd_apply_stiffness(dd_handle* h, const double* p, double* q) {
     if (e == hipSuccess) {
         if (rs == 8) {
             auto a = make_args<double>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
-            e = h->layout == DD_LAYOUT_NODE
-                    ? wdd::launch_apply_node<double>(a, h->P, h->wg, (double*)dp.p, (double*)dq.p, h->stream)
-                    : wdd::launch_apply_patch<double>(a, h->P, h->wg, (double*)dp.p, (double*)dq.p, h->stream);
+            double* x = (double*)dp.p;
+            double* y = (double*)dq.p;
+            e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_apply_node<double>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_PATCH ? wdd::launch_apply_patch1<double>(a, h->P, h->wg, x, y, h->stream)
+                                               : wdd::launch_apply_patch<double>(a, h->P, h->wg, x, y, h->stream);
         } else {
             auto a = make_args<float>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
-            e = h->layout == DD_LAYOUT_NODE
-                    ? wdd::launch_apply_node<float>(a, h->P, h->wg, (float*)dp.p, (float*)dq.p, h->stream)
-                    : wdd::launch_apply_patch<float>(a, h->P, h->wg, (float*)dp.p, (float*)dq.p, h->stream);
+            float* x = (float*)dp.p;
+            float* y = (float*)dq.p;
+            e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_apply_node<float>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_PATCH ? wdd::launch_apply_patch1<float>(a, h->P, h->wg, x, y, h->stream)
+                                               : wdd::launch_apply_patch<float>(a, h->P, h->wg, x, y, h->stream);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

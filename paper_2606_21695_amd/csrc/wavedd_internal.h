@@ -67,6 +67,11 @@ struct SweepArgs {
 template <typename Real>
 hipError_t launch_sweep_patch(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
 template <typename Real>
+hipError_t launch_sweep_patch1(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
+template <typename Real>
+hipError_t launch_apply_patch1(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                               hipStream_t s);
+template <typename Real>
 hipError_t launch_sweep_node(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
 template <typename Real>
 hipError_t launch_apply_patch(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
@@ -76,6 +81,7 @@ hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real
                              hipStream_t s);
 size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size);
 size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size);
+size_t patch1_lds_bytes(int mx, int my, int P, int wg, int nt_max, size_t real_size);
 
 // FP64 helpers for the outer iteration (blas_kernels.hip).
 struct Blas {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libwavedd.so")
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ENAN, DD_ENOTCONV, DD_ENODEV = 0, -1, -2, -3, -4, -5, -6
 DD_FP64, DD_FP32 = 0, 1
-DD_LAYOUT_AUTO, DD_LAYOUT_NODE, DD_LAYOUT_PATCH = 0, 1, 2
+DD_LAYOUT_AUTO, DD_LAYOUT_NODE, DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG = 0, 1, 2, 3
 DD_OUTER_GMRES, DD_OUTER_FIXED = 0, 1
 
 EXPORTS = [

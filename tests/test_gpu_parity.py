@@ -48,7 +48,7 @@ def _rel(a, b):
 
 
 SHAPES = [(6, 4, 3, 2, 2), (8, 8, 2, 2, 2), (4, 6, 1, 2, 3), (4, 4, 4, 2, 1), (3, 5, 3, 1, 1)]
-LAYOUTS = [1, 2]  # DD_LAYOUT_NODE, DD_LAYOUT_PATCH
+LAYOUTS = [1, 2, 3]  # DD_LAYOUT_NODE, DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -140,6 +140,14 @@ def test_sweep_converged_matches_lu(gpu_lib, layout):
     assert its.max() < 100
     assert _rel([u_gpu], u_ref) < 1e-9
     assert _rel([g_gpu], [g_ref]) < 1e-9
+
+
+def test_autotuned_layout_is_a_fitting_layout(gpu_lib):
+    W = gpu_lib
+    h, _, _ = _setup(W, 8, 8, 2, 2, 2, 10.0, _cwave)  # auto
+    lay, wg = W.dd_layout(h)
+    W.dd_destroy(h)
+    assert lay in (1, 2, 3) and wg % 64 == 0
 
 
 def test_sweep_is_deterministic(gpu_lib):
