@@ -25,6 +25,19 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 
+# HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
+# a 256 MiB copy: fetch x2.000, write x1.000), keyed by the kernel source hash
+# and (config, precision, layout); reported as null once the kernel changes.
+MEASURED_TRAFFIC = {
+    ("7680b45e72439716", "c2", "fp64", 3): 43044 * 1024,
+}
+
+
+def kernel_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
 
 def flops_per_update(P):
     """Algorithmic FLOP of one DOF-update (one leapfrog step of one node):
@@ -46,21 +59,63 @@ def cpu_baseline(wl, seconds=12.0):
     f = wl.f(X, Y)
     g0 = np.zeros(dec.n_if, dtype=complex)
     setup_s = time.perf_counter() - t_setup
-    updates, n_sub = 0.0, 0
+    updates, n_it = 0.0, 0
     t0 = time.perf_counter()
-    for l in range(dec.L):
-        sd = dec.subs[l]
-        b = dec.rhs(l, f, g0, 1.0)
-        wh.iterate(sd["A"], sd["M"], sd["H"], b, dec.omega, nts[l], np.zeros(b.size, complex))
-        updates += b.size * (nts[l] - 1)
-        n_sub += 1
-        if time.perf_counter() - t0 > seconds:
-            break
+    while time.perf_counter() - t0 < seconds:
+        for l in range(dec.L):
+            sd = dec.subs[l]
+            b = dec.rhs(l, f, g0, 1.0)
+            wh.iterate(sd["A"], sd["M"], sd["H"], b, dec.omega, nts[l],
+                       np.zeros(b.size, complex))
+            updates += b.size * (nts[l] - 1)
+            n_it += 1
+            if time.perf_counter() - t0 > seconds:
+                break
     el = time.perf_counter() - t0
     return {"value": updates / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one WaveHoltz iteration (N_t-1 leapfrog steps) on {n_sub} of {dec.L} "
-                      f"subdomains of the same workload, numpy/scipy FP64, one thread "
-                      f"({el:.1f} s; oracle setup {setup_s:.1f} s not counted)"}
+            "sample": f"{n_it} subdomain WaveHoltz iterations (N_t-1 leapfrog steps each) "
+                      f"over the {dec.L} subdomains of the same workload, numpy/scipy FP64, "
+                      f"one thread ({el:.1f} s; oracle setup {setup_s:.1f} s not counted)"}
+
+
+def variants(W, wl, u_ref, _unused, steps=2):
+    """FP32 sweeps (with FP64 refinement) and relaxed inner tolerance on the
+    same workload: solves/s, latency, DOF-updates/s and the relative L2
+    difference from the strict FP64 solution."""
+    import torch
+    out = {}
+    N = u_ref.size
+    dev = torch.device("cuda:0")
+    for name, prec, tau, relax in (("fp32_refined", W.DD_FP32, 1e-6, 0.0),
+                                   ("fp64_relaxed", W.DD_FP64, wl.tau_in, 0.1),
+                                   ("fp32_refined_relaxed", W.DD_FP32, 1e-6, 0.1)):
+        prob = W.Problem(wl, precision=prec, tau_in=tau, relax=relax)
+        f_re = torch.from_numpy(prob.f).to(dev)
+        u_re = torch.empty(N, dtype=torch.float64, device=dev)
+        u_im = torch.empty(N, dtype=torch.float64, device=dev)
+        W.dd_solve_device(prob.h, f_re, None, None, None, wl.tol, 2000, u_re, u_im,
+                          allow_notconv=True)
+        torch.cuda.synchronize()
+        lat, dof, st = [], 0.0, None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            st, rc = W.dd_solve_device(prob.h, f_re, None, None, None, wl.tol, 2000, u_re, u_im,
+                                       allow_notconv=True)
+            lat.append(time.perf_counter() - t1)
+            dof += st["dof_updates"]
+        total = time.perf_counter() - t0
+        u = u_re.cpu().numpy() + 1j * u_im.cpu().numpy()
+        out[name] = {"solves_per_s": steps / total, "dof_updates_per_s": dof / total,
+                     "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                     "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                     "outer_iters": st["outer_iters"], "refine_steps": st["refine_steps"],
+                     "true_rel_residual_interface": st["true_rel_residual"],
+                     "rel_l2_vs_fp64": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
+                     "rel_residual_global_fp64": W.dd_residual(prob.h, u, prob.f),
+                     "tau_in": tau, "relax": relax}
+        prob.close()
+    return out
 
 
 def main():
@@ -70,7 +125,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--relax", type=float, default=0.0,
+                    help="variable inner tolerance factor (0 = fixed inner tolerance)")
+    ap.add_argument("--tau-in", type=float, default=None, help="override the inner tolerance")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32 / relaxed-tolerance comparison solves")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a kernel of known "
+                         "traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the sweep shards by "
@@ -84,11 +147,20 @@ def main():
 
     W.require_gpu()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.ones_like(a)
+        torch.cuda.synchronize()
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
     wl = workloads.CONFIGS[args.config]()
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
-    tau = wl.tau_in if prec == W.DD_FP64 else max(wl.tau_in, 1e-7)
+    tau = wl.tau_in if prec == W.DD_FP64 else max(wl.tau_in, 1e-6)
+    if args.tau_in is not None:
+        tau = args.tau_in
     t0 = time.perf_counter()
-    prob = W.Problem(wl, precision=prec, tau_in=tau)
+    prob = W.Problem(wl, precision=prec, tau_in=tau, relax=args.relax)
     setup_s = time.perf_counter() - t0
     h = prob.h
     sizes = W.dd_sizes(h)
@@ -141,8 +213,9 @@ def main():
         "data": "synthetic (seeded Y-waveguide wavespeed, Gaussian source)",
         "config": {"workload": f"{args.config}: {wl.nx}x{wl.ny} elements P={P}, "
                                f"{wl.sx}x{wl.sy} subdomains, omega={wl.omega:.2f}, tol={wl.tol}",
-                   "precision": args.precision, "layout": "patch" if lay == 2 else "node",
-                   "wg_threads": wg},
+                   "precision": args.precision,
+                   "layout": {1: "node", 2: "patch", 3: "patch_xchg"}[lay],
+                   "wg_threads": wg, "tau_in": tau, "relax": args.relax},
         "solves_per_s": args.steps / total,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
@@ -155,11 +228,15 @@ def main():
         "true_rel_residual_interface": stats[-1]["true_rel_residual"],
         "setup_s": setup_s,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "sweep_patch_kernel" if lay == 2 else "sweep_node_kernel",
+                     "frac": achieved / peak,
+                     "traffic": MEASURED_TRAFFIC.get((kernel_hash(), args.config, args.precision, lay)),
+                     "kernel": {1: "sweep_node_kernel", 2: "sweep_patch1_kernel",
+                                3: "sweep_patch_kernel"}[lay],
                      "flop_per_dof_update": fl,
                      "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None},
     }
+    if not args.no_variants:
+        out["variants"] = variants(W, wl, u, lambda: None)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     prob.close()

@@ -94,16 +94,23 @@ typedef struct {
     int restart;     /* GMRES restart length m */
     int nt_override; /* > 0: use this many time steps per period in every subdomain */
     double cfl;      /* safety factor s in (0, 1] of the time-step rule */
-    int refine;      /* DD_FP32 with GMRES: FP64 iterative-refinement steps (0 = none):
-                        corrections solved with FP32 sweeps, residuals and u from FP64
-                        sweeps with inner tolerance clamp(0.01 tol, 1e-13, 1e-8) */
+    int refine;      /* extra GMRES correction passes for FP32 sweeps or relaxed inner
+                        tolerance (iterative refinement): corrections use the handle's
+                        sweeps, residuals and u come from strict FP64 sweeps (inner
+                        tolerance tau_in for FP64 handles, clamp(0.01 tol, 1e-13, 1e-8)
+                        for FP32 handles).  0 = a single pass. */
+    double relax;    /* > 0: variable inner tolerance (Sec. V: subdomain solves may be
+                        loose while the outer iteration is far from convergence).  The
+                        k-th GMRES matvec uses tau = clamp(relax * tol / r_k, tau_in, 1e-2),
+                        r_k the current relative outer residual; the true residual at
+                        exit is computed with tau_in.  0 = fixed tau_in (default). */
 } dd_options;
 
 typedef struct {
     int outer_iters;            /* outer iterations (= sweeps with sources off) */
     int sweeps;                 /* all sweep launches of the solve */
-    double rel_residual;        /* outer residual estimate ||h-(I-T)G||/||h|| at exit */
-    double true_rel_residual;   /* same, recomputed with one extra sweep at exit */
+    double rel_residual;        /* max(GMRES estimate, true residual) at exit */
+    double true_rel_residual;   /* ||h - (I-T)G|| / ||h|| from an FP64 sweep at exit */
     int64_t wh_iters_total;     /* WaveHoltz iterations summed over subdomains and sweeps */
     int wh_iters_max;           /* largest per-subdomain count in any sweep */
     int nt_min, nt_max;         /* time steps per period over subdomains */
@@ -115,7 +122,7 @@ typedef struct {
 } dd_stats;
 
 /* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
- * no N_t override, cfl 0.9, refine 4. */
+ * no N_t override, cfl 0.9, refine 4, relax 0. */
 int dd_default_options(dd_options* opt);
 
 /* Set up a problem (Sec. II-IV): mesh, degree P in [1, 4], wavespeed c > 0

@@ -386,11 +386,22 @@ int axpby(dd_handle* h, cplx a, const double2* x, cplx b, double2* y) {
 }
 
 
-// w = v - T v  (T: sweep with sources off, in the handle's precision);
-// w must not alias v.
-int matvec(dd_handle* h, const double2* v, double2* w) {
-    CHK(run_sweep(h, v, w, 0.0, false, true));
+// w = v - T v  (T: sweep with sources off, in the handle's precision, with
+// inner tolerance tau); w must not alias v.
+int matvec(dd_handle* h, const double2* v, double2* w, double tau) {
+    CHK(run_sweep(h, v, w, 0.0, false, true, h->opt.precision, tau, h->opt.max_wh));
     return axpby(h, cplx(1.0, 0.0), v, cplx(-1.0, 0.0), w);
+}
+
+// Inner tolerance of the k-th Arnoldi matvec.  Strict (tau_in) unless the
+// relaxed mode is on: inexact Krylov theory lets the matvec error grow in
+// proportion to 1 / (current residual), so tau_k = relax * tol / rel_k,
+// clamped to [tau_in, 1e-2].  The final true residual is always evaluated
+// with tau_in.
+double matvec_tau(const dd_handle* h, double tol, double rel) {
+    if (!(h->opt.relax > 0.0)) return h->opt.tau_in;
+    const double t = h->opt.relax * tol / std::max(rel, 1e-300);
+    return std::min(1e-2, std::max(h->opt.tau_in, t));
 }
 
 // Restarted GMRES(m) for (I - T) x = rhs from x = 0 (the Krylov method of
@@ -423,7 +434,7 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
         int k = 0;
         for (int j = 0; j < m; ++j) {
             double2* w = V + (int64_t)(j + 1) * ld;
-            CHK(matvec(h, V + (int64_t)j * ld, w));
+            CHK(matvec(h, V + (int64_t)j * ld, w, matvec_tau(h, tol, rel)));
             ++its;
             CHK(dots(h, V, ld, j + 1, w, h1.data()));
             HIPCHK(wdd::blas_multiaxpy(h->blas, V, ld, j + 1, w, n, h->stream));
@@ -469,8 +480,8 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
         HIPCHK(wdd::blas_combine(V, ld, k, h->d_coefs.p, x, n, 1, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         if (rel <= tol || its >= max_iter) break;
-        // r = rhs - (x - T x)
-        CHK(matvec(h, x, h->d_r.p));
+        // r = rhs - (x - T x), with the strict inner tolerance
+        CHK(matvec(h, x, h->d_r.p, h->opt.tau_in));
         CHK(axpby(h, cplx(1.0), rhs, cplx(-1.0), h->d_r.p));
         beta = norm(h, h->d_r.p);
         if (!std::isfinite(beta)) return fail(DD_ENAN, "non-finite outer residual");
@@ -524,30 +535,46 @@ int residual_sweep(dd_handle* h, bool with_f, int prec, double tau, double hnorm
     return DD_OK;
 }
 
-// Inner tolerance of the FP64 residual sweeps of a refined FP32 solve.
-double refine_tau(double tol) { return std::min(1e-8, std::max(1e-13, 0.01 * tol)); }
+// Inner tolerance of the FP64 residual sweeps: the handle's own for FP64
+// handles, clamp(0.01 tol, 1e-13, 1e-8) for FP32 handles (whose tau_in is an
+// FP32-level tolerance).
+double residual_tau(const dd_handle* h, double tol) {
+    if (h->opt.precision == DD_FP64) return h->opt.tau_in;
+    return std::min(1e-8, std::max(1e-13, 0.01 * tol));
+}
 
-// FP32 sweeps with FP64 iterative refinement on the interface system:
-// G += GMRES_fp32((I - T) d = r); r = h - (I - T) G with an FP64 sweep.
-int solve_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
-    const double tau64 = refine_tau(tol);
+// GMRES on the interface system inside an iterative-refinement loop:
+//   r = h - (I - T) G  with a strict FP64 sweep (which also returns u),
+//   G += GMRES((I - T) d = r)  with matvecs in the handle's precision and,
+//   optionally, relaxed inner tolerance,
+// until the true residual meets tol or `refine` corrections are spent.  A
+// strict FP64 solve finishes in one pass (the same iterates as plain GMRES);
+// FP32 sweeps and relaxed matvecs are corrected by the FP64 residuals.
+int solve_gmres_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
+    const double tau64 = residual_tau(h, tol);
     CHK(run_sweep(h, h->d_g0.p, h->d_h.p, 1.0, with_f, true, DD_FP64, tau64, h->opt.max_wh));
     const double hnorm = norm(h, h->d_h.p);
     if (!std::isfinite(hnorm)) return fail(DD_ENAN, "non-finite right-hand side");
     HIPCHK(hipMemsetAsync(h->d_G.p, 0, sizeof(double2) * h->n_if, h->stream));
     HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_h.p, sizeof(double2) * h->n_if,
                           hipMemcpyDeviceToDevice, h->stream));
+    const bool fp32 = h->opt.precision == DD_FP32;
+    const int passes = 1 + h->opt.refine;
     double rnorm = hnorm;
     int its_total = 0;
     double rel = hnorm > 0.0 ? 1.0 : 0.0;
+    double last_rec = rel;
     bool have_u = false;
-    for (int k = 0; k <= h->opt.refine && rel > tol && its_total < max_iter; ++k) {
-        // inner accuracy: a fixed reduction, or whatever reaches tol
-        const double inner = std::max(1e-4, tol * hnorm / rnorm);
+    for (int k = 0; k < passes && rel > tol && its_total < max_iter; ++k) {
+        // FP32 corrections aim at a fixed reduction (their operator is only
+        // FP32-accurate); FP64 ones go for the whole way
+        const double want = tol * hnorm / rnorm;
+        const double inner = fp32 ? std::max(1e-4, want) : want;
         int its = 0;
         double irel = 0.0;
         CHK(gmres(h, h->d_res.p, h->d_D.p, rnorm, inner, max_iter - its_total, &its, &irel));
         its_total += its;
+        last_rec = irel * rnorm / hnorm;
         CHK(axpby(h, cplx(1.0), h->d_D.p, cplx(1.0), h->d_G.p));
         CHK(residual_sweep(h, with_f, DD_FP64, tau64, hnorm, &rel));
         HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_tmp.p, sizeof(double2) * h->n_if,
@@ -558,7 +585,7 @@ int solve_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
     }
     if (!have_u) CHK(residual_sweep(h, with_f, DD_FP64, tau64, hnorm, &rel));
     h->st.outer_iters = its_total;
-    h->st.rel_residual = rel;
+    h->st.rel_residual = std::max(last_rec, rel);
     h->st.true_rel_residual = rel;
     h->has_state = true;
     return DD_OK;
@@ -567,20 +594,11 @@ int solve_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
 // Full solve with the device inputs staged: d_g0 (embedded boundary trace)
 // and F (source).  Leaves the stacked u in d_u and G in d_G.
 int solve_core(dd_handle* h, bool with_f, double tol, int max_iter) {
-    if (h->opt.precision == DD_FP32 && h->opt.refine > 0 && h->opt.outer == DD_OUTER_GMRES)
-        return solve_refined(h, with_f, tol, max_iter);
+    if (h->opt.outer == DD_OUTER_GMRES) return solve_gmres_refined(h, with_f, tol, max_iter);
     CHK(run_sweep(h, h->d_g0.p, h->d_h.p, 1.0, with_f, true));  // h = sweep(g_phys, src)
     const double hnorm = norm(h, h->d_h.p);
     if (!std::isfinite(hnorm)) return fail(DD_ENAN, "non-finite right-hand side");
-    if (h->opt.outer == DD_OUTER_FIXED) {
-        CHK(fixed_point(h, tol, max_iter, hnorm));
-    } else {
-        int its = 0;
-        double rel = 0.0;
-        CHK(gmres(h, h->d_h.p, h->d_G.p, hnorm, tol, max_iter, &its, &rel));
-        h->st.outer_iters = its;
-        h->st.rel_residual = rel;
-    }
+    CHK(fixed_point(h, tol, max_iter, hnorm));
     // final sweep with G + g_phys and sources: u, and T G + h for the true residual
     double rel = 0.0;
     CHK(residual_sweep(h, with_f, h->opt.precision, h->opt.tau_in, hnorm, &rel));
@@ -691,6 +709,7 @@ int dd_default_options(dd_options* o) {
     o->nt_override = 0;
     o->cfl = 0.9;
     o->refine = 4;
+    o->relax = 0.0;
     return DD_OK;
 }
 
@@ -749,6 +768,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     if (o.nt_override < 0 || o.nt_override == 1 || o.nt_override == 2)
         return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
     if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
+    if (!(o.relax >= 0.0) || !std::isfinite(o.relax)) return fail(DD_EINVAL, "relax must be >= 0");
     const int P = degree;
     const int Nx = mesh->nx * P + 1, Ny = mesh->ny * P + 1;
     const int64_t N = (int64_t)Nx * Ny;
@@ -1131,9 +1151,9 @@ int dd_solve_device(dd_handle* h, void* stream, const double* d_f_re, const doub
     if (dep) (void)hipEventDestroy(dep);
     h->st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (st) *st = h->st;
-    if (h->st.rel_residual > tol)
+    if (h->st.rel_residual > tol || h->st.true_rel_residual > tol)
         return fail(DD_ENOTCONV, "outer iteration stopped at %d iterations, residual %.3e > %.3e",
-                    h->st.outer_iters, h->st.rel_residual, tol);
+                    h->st.outer_iters, std::max(h->st.rel_residual, h->st.true_rel_residual), tol);
     return DD_OK;
 }
 
