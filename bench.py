@@ -9,8 +9,10 @@ roofline of the sweep kernel (algorithmic FLOP per launch / average launch
 time measured with HIP events on the library's stream) and the oracle timed
 on the host CPU on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3|c1]
                     [--precision fp64|fp32] [--no-cpu]
+    python bench.py --config c4      batched solves of 400 subdomains
+    python bench.py --serve          serving engine on a Poisson request stream
 """
 import argparse
 import json
@@ -118,6 +120,155 @@ def variants(W, wl, u_ref, _unused, steps=2):
     return out
 
 
+BYTES_STREAM = {"fp64": 72, "fp32": 36}   # per DOF-update, STREAM layout (9 words)
+
+
+def batch_bench(args):
+    """A batch of independent problems (400 subdomains, P in 1..4, 8..64
+    elements per subdomain side) solved together: every sweep round is one
+    batched launch per launch configuration."""
+    import torch
+    import workloads
+    from paper_2606_21695_amd import wavedd as W
+    W.require_gpu()
+    torch.cuda.set_device(0)
+    wls = workloads.c4()
+    specs = [W.workload_spec(wl) for wl in wls]
+    prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
+    tau = wls[0].tau_in if prec == W.DD_FP32 else 1e-10
+    if args.tau_in is not None:
+        tau = args.tau_in
+    t0 = time.perf_counter()
+    b = W.dd_batch_setup(specs, W.dd_default_options(precision=prec, tau_in=tau,
+                                                     relax=args.relax))
+    setup_s = time.perf_counter() - t0
+    tol = wls[0].tol
+    fs = [s_["f"] for s_ in specs]
+    for _ in range(args.warmup):
+        W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True)
+    lat, rounds, res = [], [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        us, sts, rcs, rc = W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True)
+        lat.append(time.perf_counter() - t1)
+        rounds.append(W.dd_batch_launches(b))
+        res = (us, sts, rcs)
+    total = time.perf_counter() - t0
+    us, sts, rcs = res
+    dof = sum(st["dof_updates"] for st in sts) * args.steps
+    sweep_s = max(st["sweep_seconds"] for st in sts)
+    flop = sum(flops_per_update(wl.P) * st["dof_updates"] for wl, st in zip(wls, sts))
+    achieved = flop / sweep_s / 1e12
+    rel = [W.dd_residual(W.dd_batch_handle(b, i), us[i], specs[i]["f"]) for i in range(len(us))]
+    # the paper's protocol: 5 WaveHoltz iterations on random complex interface data
+    rng = np.random.default_rng(4)
+    for i in range(len(specs)):
+        h = W.dd_batch_handle(b, i)
+        n = W.dd_sizes(h)["n_iface"]
+        W.dd_set_state(h, rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    ms5, dof5, nl5 = W.dd_batch_time_sweep(b, reps=5, fixed_iters=5)
+    W.dd_batch_destroy(b)
+    peak = PEAK_TFLOPS[args.precision]
+    out = {
+        "metric": "WaveHoltz DOF-updates/s (batched DD solves)",
+        "value": dof / total, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == W.DD_FP64 else "f32 sweep / f64 outer",
+        "data": "synthetic (seeded log-normal wavespeed, Gaussian sources)",
+        "config": {"workload": f"c4: {len(wls)} independent problems, "
+                               f"{sum(wl.sx * wl.sy for wl in wls)} subdomains, P in 1..4, "
+                               f"omega={wls[0].omega}, tol={tol}",
+                   "precision": args.precision, "tau_in": tau, "relax": args.relax},
+        "problems": len(wls),
+        "solves_per_s": len(wls) * args.steps / total,
+        "batch_latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                             "p99": 1e3 * float(np.percentile(lat, 99))},
+        "launch_rounds": rounds[-1],
+        "not_converged": int(sum(r != 0 for r in rcs)),
+        "rel_residual_global_max": float(max(rel)),
+        "setup_s": setup_s,
+        "paper_protocol_5_iterations": {"ms_per_round": ms5, "dof_updates": dof5,
+                                        "dof_updates_per_s": dof5 / (ms5 * 1e-3),
+                                        "launches_per_round": nl5},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "batched sweep launches (all layouts)",
+                     "flop_per_dof_update": "4(P+2)+16"},
+    }
+    print(json.dumps(out))
+
+
+def serve_bench(args):
+    """Serving engine on the first requests of the seeded request stream:
+    closed-loop saturated throughput first, then Poisson arrivals at a
+    fraction rho of it; latency is arrival to result."""
+    import threading
+    import torch
+    import workloads
+    from paper_2606_21695_amd import wavedd as W
+    W.require_gpu()
+    torch.cuda.set_device(0)
+    wls = workloads.c5(n_requests=args.requests)
+    specs = [W.workload_spec(wl) for wl in wls]
+    prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
+    o = W.dd_default_options(precision=prec, tau_in=wls[0].tau_in if prec == W.DD_FP32 else 1e-10,
+                             relax=args.relax)
+    budget = int(args.budget_gib * (1 << 30))
+
+    def run(arrivals):
+        e = W.dd_engine_create(budget, args.max_active, o)
+        try:
+            ids, t_sub = [], []
+            t0 = time.perf_counter()
+            for k, s_ in enumerate(specs):
+                if arrivals is not None:
+                    dt = arrivals[k] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 2000))
+            res = [W.dd_engine_wait(e, rid, s_["c"].size, allow_notconv=True)
+                   for rid, s_ in zip(ids, specs)]
+            wall = time.perf_counter() - t0
+            info = W.dd_engine_get_info(e)
+        finally:
+            W.dd_engine_destroy(e)
+        return res, wall, info
+
+    res0, wall0, info0 = run(None)
+    mu = len(specs) / wall0
+    rng = np.random.default_rng(5)
+    arr = np.cumsum(rng.exponential(1.0 / (args.rho * mu), len(specs)))
+    res, wall, info = run(arr)
+    lat = [t[2] - t[0] for _, _, t, _ in res]
+    dof = sum(st["dof_updates"] for _, st, _, _ in res)
+    out = {
+        "metric": "DD solves/s (serving, continuous batching)",
+        "value": len(specs) / wall, "unit": "solves/s", "n_gpus": 1, "steps": len(specs),
+        "warmup": 0, "ms_per_step": 1e3 * wall / len(specs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == W.DD_FP64 else "f32 sweep / f64 outer",
+        "data": "synthetic (seeded request stream: own mesh, P, omega, wavespeed, sources)",
+        "config": {"workload": f"c5: first {len(specs)} requests, Poisson arrivals at "
+                               f"rho={args.rho} of saturated throughput",
+                   "precision": args.precision, "max_active": args.max_active,
+                   "budget_gib": args.budget_gib},
+        "saturated_solves_per_s": mu,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "saturated_latency_ms": {"p50": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 50)),
+                                 "p99": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 99))},
+        "dof_updates_per_s": dof / wall,
+        "launch_rounds": info["launches"],
+        "peak_running": info["peak_running"],
+        "not_converged": int(sum(rc != 0 for *_, rc in res)),
+        "request_sizes": {"nodes_min": int(min(s_["c"].size for s_ in specs)),
+                          "nodes_max": int(max(s_["c"].size for s_ in specs))},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +282,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
+    ap.add_argument("--serve", action="store_true", help="serving engine on the c5 stream")
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--rho", type=float, default=0.8)
+    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -141,6 +297,10 @@ def main():
                                    "path is built; use --gpus 1"}))
         sys.exit(2)
 
+    if args.serve:
+        return serve_bench(args)
+    if args.config == "c4":
+        return batch_bench(args)
     import torch
     import workloads
     from paper_2606_21695_amd import wavedd as W
@@ -198,6 +358,13 @@ def main():
     u = (u_re.cpu().numpy() + 1j * u_im.cpu().numpy())
     rel_res = W.dd_residual(h, u, prob.f)
     nt = W.dd_time_steps(h)
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak}
+    if lay == 4:
+        gbs = BYTES_STREAM[args.precision] * dof / sweep_s / 1e9 if sweep_s > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                "frac": gbs / 8000.0, "byte_per_dof_update": BYTES_STREAM[args.precision],
+                "alu_tflops": achieved}
     out = {
         "metric": "WaveHoltz DOF-updates/s (DD solve, FP64 outer)",
         "value": dof / total,
@@ -214,7 +381,7 @@ def main():
         "config": {"workload": f"{args.config}: {wl.nx}x{wl.ny} elements P={P}, "
                                f"{wl.sx}x{wl.sy} subdomains, omega={wl.omega:.2f}, tol={wl.tol}",
                    "precision": args.precision,
-                   "layout": {1: "node", 2: "patch", 3: "patch_xchg"}[lay],
+                   "layout": {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay],
                    "wg_threads": wg, "tau_in": tau, "relax": args.relax},
         "solves_per_s": args.steps / total,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
@@ -227,13 +394,12 @@ def main():
         "rel_residual_global_fp64": rel_res,
         "true_rel_residual_interface": stats[-1]["true_rel_residual"],
         "setup_s": setup_s,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": MEASURED_TRAFFIC.get((kernel_hash(), args.config, args.precision, lay)),
-                     "kernel": {1: "sweep_node_kernel", 2: "sweep_patch1_kernel",
-                                3: "sweep_patch_kernel"}[lay],
-                     "flop_per_dof_update": fl,
-                     "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None},
+        "roofline": dict(roof, **{
+            "traffic": MEASURED_TRAFFIC.get((kernel_hash(), args.config, args.precision, lay)),
+            "kernel": {1: "sweep_node_kernel", 2: "sweep_patch1_kernel",
+                       3: "sweep_patch_kernel", 4: "sweep_stream_kernel"}[lay],
+            "flop_per_dof_update": fl,
+            "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None}),
     }
     if not args.no_variants:
         out["variants"] = variants(W, wl, u, lambda: None)

@@ -68,6 +68,7 @@ extern "C" {
 #define DD_LAYOUT_NODE 1        /* one DOF per thread, state in registers + LDS */
 #define DD_LAYOUT_PATCH 2       /* one element patch (P*P DOFs) per thread, one barrier/step */
 #define DD_LAYOUT_PATCH_XCHG 3  /* same ownership, partial-sum exchange, two barriers/step */
+#define DD_LAYOUT_STREAM 4      /* any size: state streamed through L2 / HBM, one barrier/step */
 
 #define DD_OUTER_GMRES 0
 #define DD_OUTER_FIXED 1
@@ -207,8 +208,127 @@ int dd_set_state(dd_handle* h, const double* G);
  * one launch (sum over subdomains of nloc*(N_t-1)*iterations; may be NULL). */
 int dd_time_sweep(dd_handle* h, int reps, int fixed_iters, double* ms, double* dof_updates);
 
-/* Current layout (DD_LAYOUT_NODE or DD_LAYOUT_PATCH) and threads/workgroup. */
+/* Layout in use (DD_LAYOUT_NODE .. DD_LAYOUT_STREAM) and threads/workgroup. */
 int dd_layout(const dd_handle* h, int* layout, int* wg_threads);
+
+/* Coordinates of the global GLL nodes of a mesh (N each, flat index
+ * j * Nx + i), computed on the host without a handle or a device: the
+ * sampling points of wavespeed and f for dd_setup / dd_solve (Sec. IV,
+ * nodal GLL basis). */
+int dd_mesh_coords(const dd_mesh* mesh, int degree, double* x, double* y);
+
+/* ------------------------------------------------------------------------
+ * Batches: several independent problems whose sweeps share launches.
+ *
+ * The DD method makes every subdomain solve independent within a sweep
+ * (Sec. III), so subdomains of different problems can share one launch just
+ * as the subdomains of one problem do (Sec. VI: all subdomains of a sweep in
+ * one kernel launch).  A batch places its problems in one device store; each
+ * problem runs its own FP64 outer iteration, and every round of sweeps is a
+ * batched launch per launch configuration (precision, degree, layout,
+ * workgroup class) whose work list is ordered by estimated cost (DOFs x
+ * (N_t - 1) x WaveHoltz iterations of the previous sweep), longest first.
+ * Layouts are autotuned once per subdomain shape (mx, my, P, precision).
+ * ------------------------------------------------------------------------ */
+typedef struct dd_batch dd_batch;
+
+/* One problem: the arguments of dd_setup (wavespeed is copied). */
+typedef struct {
+    dd_mesh mesh;
+    int degree;
+    const double* wavespeed;   /* N values at the global nodes, c > 0 */
+    double omega;
+    dd_partition part;
+} dd_problem;
+
+/* Set up n >= 1 problems with shared options (opt may be NULL).  Errors name
+ * the failing problem; nothing is allocated on failure. */
+int dd_batch_setup(dd_batch** out, int n, const dd_problem* probs, const dd_options* opt);
+void dd_batch_destroy(dd_batch* b);
+
+/* Handle of problem i (owned by the batch; valid until dd_batch_destroy) for
+ * dd_sizes, dd_node_coords, dd_time_steps, dd_residual, dd_get_state,
+ * dd_set_state, dd_layout.  Do not pass it to dd_destroy, and do not solve
+ * or sweep through it while dd_batch_solve runs. */
+int dd_batch_handle(dd_batch* b, int i, dd_handle** h);
+
+/* Solve all problems, each as dd_solve would (same arguments per problem:
+ * arrays of n pointers; f_re, f_im may be NULL or hold NULL entries), with
+ * their sweeps batched.  st and rc (n entries each) may be NULL.  Returns
+ * DD_OK when every problem converged, DD_ENOTCONV when some did not (their
+ * u and stats are written), or the first other error. */
+int dd_batch_solve(dd_batch* b, const double* const* f_re, const double* const* f_im, double tol,
+                   int max_iter, double* const* u_re, double* const* u_im, dd_stats* st, int* rc);
+
+/* Time batched sweep launches over every subdomain of every problem (the
+ * paper's DD-cycle timing, Sec. VII-A): inputs are each problem's current
+ * outer state G, sources off, exactly fixed_iters >= 1 WaveHoltz iterations
+ * per subdomain.  Returns the average milliseconds per round of launches
+ * over `reps` rounds after one warm-up, the DOF-updates of one round, and the
+ * number of launches in a round. */
+int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, double* dof_updates,
+                        int* launches);
+
+/* Batched launch rounds issued by the last dd_batch_solve. */
+int dd_batch_launches(const dd_batch* b, int64_t* launches);
+
+/* ------------------------------------------------------------------------
+ * Serving engine: solves submitted one at a time, run concurrently with
+ * continuous batching.
+ *
+ * A request is one dd_solve.  The engine admits queued requests in arrival
+ * order while the number of running solves is below max_active and their
+ * device footprint fits the HBM budget: a share of the budget is one device
+ * store holding every admitted problem's sweep arrays (ranges handed out by
+ * a first-fit allocator), the rest pays for the per-request outer-iteration
+ * vectors.  Each running request advances its own FP64 outer iteration on
+ * its own host thread and stream; every round of sweeps is one batched
+ * launch over all running requests' subdomains (as for dd_batch_solve), and
+ * requests join and retire between rounds.  Results stay with the engine
+ * until dd_engine_wait collects them.
+ * ------------------------------------------------------------------------ */
+typedef struct dd_engine dd_engine;
+
+#define DD_REQ_QUEUED 0
+#define DD_REQ_RUNNING 1
+#define DD_REQ_DONE 2
+
+typedef struct {
+    int64_t queued, running, done;   /* requests in each state */
+    int64_t launches;                /* batched launch rounds so far */
+    int64_t peak_running;
+    size_t budget_bytes;             /* as given */
+    size_t store_bytes;              /* device store */
+    size_t request_bytes;            /* held by running requests */
+} dd_engine_info;
+
+/* hbm_budget_bytes: device memory the engine may use (>= 64 MiB);
+ * max_active >= 1 concurrent solves; opt applies to every request (NULL:
+ * defaults). */
+int dd_engine_create(dd_engine** out, size_t hbm_budget_bytes, int max_active,
+                     const dd_options* opt);
+/* Cancels queued requests, waits for running ones, frees everything. */
+void dd_engine_destroy(dd_engine* e);
+
+/* Queue a request (problem as for dd_setup, source as for dd_solve; all
+ * arrays are copied; boundary data g = 0).  Validation and host-side set-up
+ * happen here (errors are returned before queueing); a request larger than
+ * the engine's whole store or budget fails with DD_ENOMEM.  *id identifies it
+ * for dd_engine_status / dd_engine_wait. */
+int dd_engine_submit(dd_engine* e, const dd_problem* prob, const double* f_re, const double* f_im,
+                     double tol, int max_iter, int64_t* id);
+
+/* DD_REQ_QUEUED, DD_REQ_RUNNING or DD_REQ_DONE. */
+int dd_engine_status(dd_engine* e, int64_t id, int* state);
+
+/* Block until request id is done, copy its glued solution (N values each;
+ * may be NULL) and stats, and release it.  times (may be NULL) receives the
+ * submit, start and completion times in seconds on the engine's clock.
+ * Returns the request's own code (DD_OK, DD_ENOTCONV, ...). */
+int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stats* st,
+                   double* times);
+
+int dd_engine_get_info(dd_engine* e, dd_engine_info* info);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,8 @@
 //  * NODE: one thread per node (<= 1024 nodes); p double-buffered in LDS
 //    with zero padding, so the (2P+1)-point 1D windows need no bounds
 //    checks (one barrier per step).
+//  * STREAM: any subdomain size; the NODE arithmetic with the state in
+//    device memory (zero-padded p grids, one barrier per step).
 // Both stage the per-step filter / forcing tables of the subdomain in LDS
 // (broadcast reads) when the subdomain starts.
 #include "wavedd_internal.h"
@@ -473,7 +475,9 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
     const Real* TAB = C.TAB;
     const double pd0c = d.pd0c, pd0s = d.pd0s;
     int it = 0;
-    for (int m = 0; m < A.max_wh; ++m) {
+    const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
+    const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
 #pragma unroll
         for (int a = 0; a < P; ++a)
@@ -638,7 +642,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;  // non-finite iterate: stop, reported by the host
-        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -905,7 +909,9 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const double pd0c = d.pd0c, pd0s = d.pd0s;
     const Real kPP = C.K(P, P);
     int it = 0;
-    for (int m = 0; m < A.max_wh; ++m) {
+    const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
+    const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
 #pragma unroll
         for (int a = 0; a < P; ++a)
@@ -1064,7 +1070,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -1227,7 +1233,9 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
     const int nt = d.nt;
     const Real* TAB = C.TAB;
     int it = 0;
-    for (int m = 0; m < A.max_wh; ++m) {
+    const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
+    const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    for (int m = 0; m < max_wh; ++m) {
         if (C.has) slot_init(s, A, d, m > 0, TAB[2], TAB[3]);
         for (int nu = 1; nu < nt; ++nu) {
             Real* buf = (nu & 1) ? C.buf1 : C.buf0;
@@ -1249,7 +1257,7 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -1289,7 +1297,228 @@ __global__ void __launch_bounds__(kMaxWG) apply_node_kernel(const SweepArgs<Real
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// STREAM layout (subdomains larger than one CU's LDS + register file)
+// ---------------------------------------------------------------------------
+// The workgroup strides over the subdomain's nodes (thread t: nodes t,
+// t + WG, ...).  p lives in two zero-padded grids in device memory
+// (double-buffered: one barrier per step), pdot and the filter sums in
+// node-indexed arrays read and written once per step, so every step moves
+// O(1) words per node through L2 / HBM.  The arithmetic per node is the
+// NODE layout's, in the same order.
+
+// LDS (after 40 doubles for reductions): window table (kMaxP+2) x
+// (2 kMaxP+1), reference element matrix, per-step tables.
+constexpr int kStreamWT = (kMaxP + 2) * (2 * kMaxP + 1);
+constexpr int kStreamTab = (kStreamWT + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
+
+// Window class of local node k on a line of nl nodes: 1..P-1 element
+// interior offset, 0 interior vertex (two elements), P first node, P+1 last.
+template <int P>
+__device__ __forceinline__ int stream_class(int k, int nl) {
+    return k == 0 ? P : (k == nl - 1 ? P + 1 : k % P);
+}
+
+template <typename Real, int P>
+__device__ __forceinline__ void stream_tables(Real* lds, const double (*K1)[kMaxP + 1]) {
+    constexpr int W = 2 * P + 1;
+    Real* KL = lds + kStreamWT;
+    const int tid = threadIdx.x;
+    if (tid < (P + 1) * (P + 1)) KL[tid] = (Real)K1[tid / (P + 1)][tid % (P + 1)];
+    __syncthreads();
+    if (tid < P + 2) {
+        // representative node of each class: (node, elements on the line)
+        const int k = tid == P ? 0 : (tid == P + 1 ? P : (tid == 0 ? P : tid));
+        const int nel = tid == 0 ? 2 : 1;
+        Real w[W];
+        window_coeffs<Real, P>(w, k, nel, KL);
+#pragma unroll
+        for (int j = 0; j < W; ++j) lds[tid * W + j] = w[j];
+    }
+}
+
+template <typename Real, int P, bool HAS_SRC>
+__device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
+                                  double* red) {
+    constexpr int W = 2 * P + 1;
+    const int nxl = d.nxl, nyl = d.nyl, tid = threadIdx.x, bd = blockDim.x;
+    const int nloc = nxl * nyl, stride = nxl + 2 * kMaxP;
+    const int di = bd % nxl, dj = bd / nxl;
+    stream_tables<Real, P>(lds, A.K1[P]);
+    stage_tables(A, d, lds + kStreamTab);
+    const Real* WT = lds;
+    const Real* TAB = lds + kStreamTab;
+    Real* p0 = A.ws_p + d.ws_off;
+    Real* p1 = p0 + stream_pad_nodes(nxl, nyl);
+    Real* PD = A.ws_s + d.node_off;
+    Real* VR = PD + A.ws_stride;
+    Real* VI = VR + A.ws_stride;
+    Real* BR = VI + A.ws_stride;
+    Real* BI = BR + A.ws_stride;
+    const Real* AL = A.coef.alpha + d.node_off;
+    const Real* BX = A.coef.betaX + d.node_off;
+    const Real* BY = A.coef.betaY + d.node_off;
+    // beta * b (eq. (4) right-hand side with the interface data)
+    {
+        int il = tid % nxl, jl = tid / nxl;
+        for (int n = tid; n < nloc; n += bd) {
+            const double be = (double)A.coef.beta[d.node_off + n];
+            const double2 b = assemble_b(A, d, il, jl);
+            BR[n] = (Real)(be * b.x);
+            BI[n] = (Real)(be * b.y);
+            il += di;
+            jl += dj;
+            if (il >= nxl) { il -= nxl; ++jl; }
+        }
+    }
+    __syncthreads();
+    const Real sig = (Real)d.sigma;
+    const int nt = d.nt;
+    int it = 0;
+    const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
+    const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    for (int m = 0; m < max_wh; ++m) {
+        // u -> (p^1, pdot^{1/2}, v)
+        {
+            const Real k0 = TAB[2], kh0 = TAB[3];
+            int il = tid % nxl, jl = tid / nxl;
+            for (int n = tid; n < nloc; n += bd) {
+                Real p = Real(0), pd = Real(0);
+                if (m > 0) {
+                    const double2 u = A.u[d.node_off + n];
+                    p = (Real)u.x;
+                    pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
+                }
+                VR[n] = k0 * p;
+                VI[n] = kh0 * pd;
+                PD[n] = pd;
+                p1[(jl + kMaxP) * stride + il + kMaxP] = fma(sig, pd, p);
+                il += di;
+                jl += dj;
+                if (il >= nxl) { il -= nxl; ++jl; }
+            }
+        }
+        double dsum = 0.0, nsum = 0.0;
+        for (int nu = 1; nu < nt; ++nu) {
+            __syncthreads();
+            const Real* cur = (nu & 1) ? p1 : p0;
+            Real* nxt = (nu & 1) ? p0 : p1;
+            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
+            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
+            const bool last = nu == nt - 1;
+            int il = tid % nxl, jl = tid / nxl;
+#pragma nounroll
+            for (int n = tid; n < nloc; n += bd) {
+                const int pidx = (jl + kMaxP) * stride + il + kMaxP;
+                const Real* wx = WT + stream_class<P>(il, nxl) * W;
+                const Real* wy = WT + stream_class<P>(jl, nyl) * W;
+                Real X = Real(0), Y = Real(0);
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    X = fma(wx[j], cur[pidx + j - P], X);
+                    Y = fma(wy[j], cur[pidx + (j - P) * stride], Y);
+                }
+                const Real p = cur[pidx];
+                const bool bnd = il == 0 || il == nxl - 1 || jl == 0 || jl == nyl - 1;
+                Real al = Real(1), br = Real(0), bi = Real(0);
+                if (bnd) al = AL[n];
+                if (HAS_SRC || bnd) {
+                    br = BR[n];
+                    bi = BI[n];
+                }
+                Real t = br * c;
+                t = fma(bi, sv, t);
+                t = fma(-BX[n], X, t);
+                t = fma(-BY[n], Y, t);
+                const Real pd = fma(al, PD[n], t);
+                const Real vr = fma(k1, p, VR[n]);
+                const Real vi = fma(k2, pd, VI[n]);
+                if (!last) {
+                    PD[n] = pd;
+                    VR[n] = vr;
+                    VI[n] = vi;
+                    nxt[pidx] = fma(sig, pd, p);
+                } else {
+                    // u_new = (2/N_t) v (eq. (7)); fixed-point residual sums
+                    const double ur = d.two_over_nt * (double)vr;
+                    const double ui = d.two_over_nt * (double)vi;
+                    double orr = 0.0, oi = 0.0;
+                    if (m > 0) {
+                        const double2 o = A.u[d.node_off + n];
+                        orr = o.x;
+                        oi = o.y;
+                    }
+                    dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+                    nsum += ur * ur + ui * ui;
+                    A.u[d.node_off + n] = make_double2(ur, ui);
+                }
+                il += di;
+                jl += dj;
+                if (il >= nxl) { il -= nxl; ++jl; }
+            }
+        }
+        block_sum2(dsum, nsum, red);
+        it = m + 1;
+        if (!(dsum == dsum)) break;
+        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
+    }
+    __threadfence_block();
+    __syncthreads();
+    exchange(A, d);
+    if (threadIdx.x == 0) A.wh_iters[item] = it;
+}
+
+template <typename Real, int P, bool HAS_SRC>
+__global__ void __launch_bounds__(kMaxWG) sweep_stream_kernel(const SweepArgs<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const SubDesc d = A.desc[item];
+        sweep_stream_item<Real, P, HAS_SRC>(A, d, item, lds, red);
+        __syncthreads();
+    }
+}
+
+// q = A p per subdomain (node-indexed, unpadded; the windows are bounds
+// checked) with the STREAM layout's window tables.
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) apply_stream_kernel(const SweepArgs<Real> A,
+                                                              const Real* pin, Real* qout) {
+    constexpr int W = 2 * P + 1;
+    extern __shared__ double smem_d[];
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    const SubDesc d = A.desc[blockIdx.x];
+    stream_tables<Real, P>(lds, A.K1[P]);
+    __syncthreads();
+    const int nxl = d.nxl, nyl = d.nyl, nloc = nxl * nyl;
+    const double* wxp = A.w1d + d.w_off;
+    const double* wyp = wxp + nxl;
+    const Real* p = pin + d.node_off;
+    for (int n = threadIdx.x; n < nloc; n += blockDim.x) {
+        const int il = n % nxl, jl = n / nxl;
+        const Real* wx = lds + stream_class<P>(il, nxl) * W;
+        const Real* wy = lds + stream_class<P>(jl, nyl) * W;
+        Real X = Real(0), Y = Real(0);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int i2 = il + j - P, j2 = jl + j - P;
+            const Real px = (i2 >= 0 && i2 < nxl) ? p[jl * nxl + i2] : Real(0);
+            const Real py = (j2 >= 0 && j2 < nyl) ? p[j2 * nxl + il] : Real(0);
+            X = fma(wx[j], px, X);
+            Y = fma(wy[j], py, Y);
+        }
+        qout[d.node_off + n] = (Real)(d.sx_ref * wyp[jl]) * X + (Real)(d.sy_ref * wxp[il]) * Y;
+    }
+}
+
 }  // namespace
+
+size_t stream_lds_bytes(int P, int nt_max, size_t real_size) {
+    (void)P;
+    return 40 * sizeof(double) + ((size_t)kStreamTab + 4 * (size_t)nt_max) * real_size;
+}
 
 size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size) {
     return 40 * sizeof(double) + (size_t)patch_lds(mx, my, P, nt_max).total * real_size;
@@ -1435,5 +1664,41 @@ template hipError_t launch_apply_node<double>(const SweepArgs<double>&, int, int
                                               double*, hipStream_t);
 template hipError_t launch_apply_node<float>(const SweepArgs<float>&, int, int, const float*,
                                              float*, hipStream_t);
+
+template <typename Real>
+hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    const bool src = a.Fre != nullptr && a.src != 0.0;
+    if (wg > kMaxWG) return hipErrorInvalidValue;
+#define L(PP)                                                                                    \
+    if (src)                                                                                     \
+        hipLaunchKernelGGL((sweep_stream_kernel<Real, PP, true>), dim3(a.n_items), dim3(wg), lds, \
+                           s, a);                                                                \
+    else                                                                                         \
+        hipLaunchKernelGGL((sweep_stream_kernel<Real, PP, false>), dim3(a.n_items), dim3(wg),     \
+                           lds, s, a)
+    WDD_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_apply_stream(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                               hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    if (wg > kMaxWG) return hipErrorInvalidValue;
+#define L(PP) \
+    hipLaunchKernelGGL((apply_stream_kernel<Real, PP>), dim3(a.n_items), dim3(wg), lds, s, a, p, q)
+    WDD_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep_stream<double>(const SweepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_sweep_stream<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_apply_stream<double>(const SweepArgs<double>&, int, int, const double*,
+                                                double*, hipStream_t);
+template hipError_t launch_apply_stream<float>(const SweepArgs<float>&, int, int, const float*,
+                                               float*, hipStream_t);
 
 }  // namespace wdd

@@ -7,14 +7,20 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "wavedd_internal.h"
@@ -189,7 +195,117 @@ struct DBuf {
     void free() {
         if (p) (void)hipFree(p);
         p = nullptr;
+        n = 0;
     }
+};
+
+// First-fit allocator of index ranges in [0, cap), coalescing on release.
+struct RangeAlloc {
+    int64_t cap = 0, used = 0;
+    std::map<int64_t, int64_t> free_;  // start -> length
+    void init(int64_t c) {
+        cap = c;
+        used = 0;
+        free_.clear();
+        if (c > 0) free_[0] = c;
+    }
+    // start of a free range of n entries, or -1
+    int64_t alloc(int64_t n) {
+        if (n <= 0) return 0;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const int64_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[off + n] = len - n;
+            used += n;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n) {
+        if (n <= 0 || off < 0) return;
+        used -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Store;
+
+// A pending sweep of one problem, waiting for the next batched launch.
+struct SweepReq {
+    dd_handle* h;
+    const double2* g_in;
+    double2* g_out;
+    double src;
+    bool with_f;
+    int prec;
+    double tau;
+    int max_wh;
+    bool done = false;
+    int rc = 0;
+};
+
+// Rendezvous of the problems solving concurrently on one store: each
+// problem's host thread posts its sweep and blocks; once every active
+// problem has posted, the last one launches all posted sweeps together.
+struct Sched {
+    std::mutex mu;
+    std::condition_variable cv;
+    int active = 0;
+    bool launching = false;
+    std::vector<SweepReq*> pending;
+    std::atomic<int64_t> launches{0};
+    std::string err;
+};
+
+// Device arrays that sweep kernels index by global offsets: per node,
+// per interface slot, per work item, per table entry.  A handle created by
+// dd_setup owns a store sized for itself; batches and engines place many
+// problems in one store (disjoint ranges), so one launch covers them all.
+struct Store {
+    int dev = 0;
+    bool shared = false;      // several problems (exchange buffers, work lists)
+    int64_t align = 1;        // range granularity
+    int64_t cap_node = 0, cap_if = 0, cap_item = 0, cap_tab = 0, cap_w1d = 0, cap_wsp = 0;
+    RangeAlloc a_node, a_if, a_item, a_tab, a_w1d, a_wsp;
+    struct PrecBuf {
+        DBuf<char> coef;      // alpha, betaX, betaY, beta (stride cap_node)
+        DBuf<char> tab;       // kap, kaph, cs, sn (stride cap_tab)
+        DBuf<char> F;         // Fre, Fim (stride cap_node)
+        bool present = false;
+    } pb[2];
+    DBuf<wdd::SubDesc> d_desc;
+    DBuf<double> d_w1d, d_kside, d_area;
+    DBuf<int> d_gidx, d_iters, d_is_iface;
+    DBuf<int64_t> d_trace_idx;
+    DBuf<double2> d_u;
+    DBuf<double> d_wsp, d_wss;       // STREAM layout workspace
+    DBuf<double2> d_gin, d_gout;     // shared: per-problem sweep input / output ranges
+    DBuf<wdd::SubDesc> d_work;       // shared: work lists of batched launches
+    DBuf<int> d_work_iters;
+    wdd::SubDesc* h_work = nullptr;  // pinned staging of the work lists
+    int* h_work_iters = nullptr;
+    hipStream_t stream = nullptr;
+    static constexpr int kGroupStreams = 4;
+    hipStream_t gs[kGroupStreams] = {};
+    hipEvent_t ev_in = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t gev[kGroupStreams] = {};
+    size_t bytes = 0;
+    std::mutex mu;            // allocators, layout cache
+    std::map<std::tuple<int, int, int, int>, int> layout_cache;  // (mx, my, P, prec) -> layout
+    Sched sched;
 };
 
 }  // namespace
@@ -208,34 +324,30 @@ struct dd_handle {
     std::vector<double> c;           // wavespeed at global nodes
     std::vector<int> nt;             // per subdomain
     int nt_max = 0;
-    std::vector<wdd::SubDesc> desc;
+    std::vector<wdd::SubDesc> desc;  // global offsets into the store
     int layout = DD_LAYOUT_PATCH, wg = 256;
+    size_t lds[2] = {0, 0};          // dynamic LDS of a launch, FP64 / FP32
     int dev = 0;
     hipStream_t stream = nullptr;
-    // device data
-    DBuf<wdd::SubDesc> d_desc;
-    // per-precision sweep data: [0] FP64 (always), [1] FP32 (FP32 handles)
-    struct PrecBuf {
-        DBuf<char> coef;             // alpha, betaX, betaY, beta
-        DBuf<char> tab;              // kap, kaph, cs, sn
-        DBuf<char> F;                // Fre, Fim (per solve)
-        size_t lds_bytes = 0;
-        bool present = false;
-    } pb[2];
-    int64_t tab_len = 0;
-    DBuf<double> d_w1d, d_kside, d_area;
-    DBuf<int> d_gidx, d_iters, d_is_iface;
-    DBuf<int64_t> d_trace_idx;
-    DBuf<double2> d_u;               // stacked subdomain iterate
+    // placement in the store
+    Store* store = nullptr;
+    bool own_store = false;
+    bool batched = false;            // sweeps go through the store's rendezvous
+    int64_t node_base = 0, if_base = 0, item_base = 0, tab_base = 0, w1d_base = 0, wsp_base = 0;
+    int64_t node_len = 0, if_len = 0, item_len = 0, tab_len = 0, w1d_len = 0, wsp_len = 0;
+    bool placed = false;
+    // per-problem device vectors of the outer iteration
     DBuf<double2> d_V;               // GMRES basis (restart + 1) x ld
     DBuf<double2> d_G, d_h, d_tmp, d_g0, d_r, d_coefs, d_D, d_res;
     DBuf<double> d_fre, d_fim, d_gre, d_gim, d_ure, d_uim;  // staging for host API
     DBuf<double> d_wxg, d_wyg, d_Mg, d_Hg;                 // global operator data
     DBuf<double2> d_work;            // N complex scratch
+    size_t own_bytes = 0;            // device bytes of the vectors above
     int64_t ld = 0;
     wdd::Blas blas;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<int> iters_host;
+    std::vector<int> last_iters;     // per subdomain, for longest-first ordering
     double K1all[wdd::kMaxP + 1][wdd::kMaxP + 1][wdd::kMaxP + 1];  // reference stiffness per P
     bool has_state = false;
     // stats of the current solve
@@ -248,15 +360,15 @@ size_t real_size(const dd_handle* h) { return h->opt.precision == DD_FP32 ? 4 : 
 size_t prec_size(int prec) { return prec == DD_FP32 ? 4 : 8; }
 int prec_index(int prec) { return prec == DD_FP32 ? 1 : 0; }
 
+// Launch arguments with the store's arrays; desc / n_items / wh_iters /
+// lds / nt_max are filled by the caller.
 template <typename Real>
-wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out, double src,
-                               bool with_f, double tau, int max_wh) {
-    const dd_handle::PrecBuf& B = h->pb[sizeof(Real) == 4 ? 1 : 0];
+wdd::SweepArgs<Real> store_args(const Store* S, const double2* g_in, double2* g_out, double src,
+                                bool with_f, double tau, int max_wh, const double (*K1)[wdd::kMaxP + 1][wdd::kMaxP + 1]) {
+    const Store::PrecBuf& B = S->pb[sizeof(Real) == 4 ? 1 : 0];
     wdd::SweepArgs<Real> a{};
-    a.desc = h->d_desc.p;
-    a.n_items = (int)h->L;
     Real* coef = reinterpret_cast<Real*>(B.coef.p);
-    const int64_t n = h->L * h->nloc;
+    const int64_t n = S->cap_node;
     a.coef.alpha = coef;
     a.coef.betaX = coef + n;
     a.coef.betaY = coef + 2 * n;
@@ -264,23 +376,38 @@ wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out
     Real* F = reinterpret_cast<Real*>(B.F.p);
     a.Fre = with_f ? F : nullptr;
     a.Fim = with_f ? F + n : nullptr;
-    a.w1d = h->d_w1d.p;
-    a.kside = h->d_kside.p;
+    a.w1d = S->d_w1d.p;
+    a.kside = S->d_kside.p;
     Real* tab = reinterpret_cast<Real*>(B.tab.p);
     a.kap = tab;
-    a.kaph = tab + h->tab_len;
-    a.cs = tab + 2 * h->tab_len;
-    a.sn = tab + 3 * h->tab_len;
+    a.kaph = tab + S->cap_tab;
+    a.cs = tab + 2 * S->cap_tab;
+    a.sn = tab + 3 * S->cap_tab;
     a.g_in = g_in;
     a.g_out = g_out;
     a.src = src;
-    a.u = h->d_u.p;
-    a.wh_iters = h->d_iters.p;
+    a.u = S->d_u.p;
     a.tau = tau;
     a.max_wh = max_wh;
-    a.lds_bytes = B.lds_bytes;
+    a.ws_p = reinterpret_cast<Real*>(S->d_wsp.p);
+    a.ws_s = reinterpret_cast<Real*>(S->d_wss.p);
+    a.ws_stride = n;
+    std::memcpy(a.K1, K1, sizeof(a.K1));
+    return a;
+}
+
+// Arguments of a launch over this handle's subdomains; g_in / g_out are
+// indexed by the store's interface offsets.
+template <typename Real>
+wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out, double src,
+                               bool with_f, double tau, int max_wh) {
+    wdd::SweepArgs<Real> a = store_args<Real>(h->store, g_in, g_out, src, with_f, tau, max_wh,
+                                              h->K1all);
+    a.desc = h->store->d_desc.p + h->item_base;
+    a.n_items = (int)h->L;
+    a.wh_iters = h->store->d_iters.p + h->item_base;
+    a.lds_bytes = h->lds[sizeof(Real) == 4 ? 1 : 0];
     a.nt_max = h->nt_max;
-    std::memcpy(a.K1, h->K1all, sizeof(a.K1));
     return a;
 }
 
@@ -291,13 +418,15 @@ int patch_threads(const dd_handle* h) {
 }
 
 int layout_threads(const dd_handle* h, int layout) {
-    const int t = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl : patch_threads(h);
+    int t = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl : patch_threads(h);
+    if (layout == DD_LAYOUT_STREAM) t = (int)std::min<int64_t>(1024, h->nloc);
     return ((t + 63) / 64) * 64;
 }
 
 size_t layout_lds(const dd_handle* h, int layout, int prec) {
     const size_t rs = prec_size(prec);
     if (layout == DD_LAYOUT_NODE) return wdd::node_lds_bytes(h->nxl, h->nyl, h->nt_max, rs);
+    if (layout == DD_LAYOUT_STREAM) return wdd::stream_lds_bytes(h->P, h->nt_max, rs);
     if (layout == DD_LAYOUT_PATCH_XCHG) return wdd::patch_lds_bytes(h->mx, h->my, h->P, h->nt_max, rs);
     return wdd::patch1_lds_bytes(h->mx, h->my, h->P, layout_threads(h, layout), h->nt_max, rs);
 }
@@ -305,52 +434,292 @@ size_t layout_lds(const dd_handle* h, int layout, int prec) {
 void layout_config(dd_handle* h, int layout) {
     h->layout = layout;
     h->wg = layout_threads(h, layout);
-    for (int prec : {DD_FP64, DD_FP32})
-        h->pb[prec_index(prec)].lds_bytes = layout_lds(h, layout, prec);
+    for (int prec : {DD_FP64, DD_FP32}) h->lds[prec_index(prec)] = layout_lds(h, layout, prec);
 }
 
 // Fits in one workgroup for every precision the handle carries (FP64
 // always, for the refinement residuals of FP32 handles too).
 bool layout_fits(const dd_handle* h, int layout) {
+    if (layout == DD_LAYOUT_STREAM) return layout_lds(h, layout, DD_FP64) <= kLdsLimit;
     const bool threads_ok = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl <= 1024 : patch_threads(h) <= 512;
     return threads_ok && layout_lds(h, layout, DD_FP64) <= kLdsLimit;
 }
 
-// One sweep launch: g_out = sweep(g_in, src), u = subdomain solutions.
-int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
-              bool timed, int prec, double tau, int max_wh) {
-    hipStream_t s = h->stream;
-    if (timed) HIPCHK(hipEventRecord(h->ev0, s));
-    hipError_t e;
-    if (prec == DD_FP32) {
-        auto a = make_args<float>(h, g_in, g_out, src, with_f, tau, max_wh);
-        e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_sweep_node<float>(a, h->P, h->wg, s)
-            : h->layout == DD_LAYOUT_PATCH ? wdd::launch_sweep_patch1<float>(a, h->P, h->wg, s)
-                                           : wdd::launch_sweep_patch<float>(a, h->P, h->wg, s);
-    } else {
-        auto a = make_args<double>(h, g_in, g_out, src, with_f, tau, max_wh);
-        e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_sweep_node<double>(a, h->P, h->wg, s)
-            : h->layout == DD_LAYOUT_PATCH ? wdd::launch_sweep_patch1<double>(a, h->P, h->wg, s)
-                                           : wdd::launch_sweep_patch<double>(a, h->P, h->wg, s);
+template <typename Real>
+hipError_t launch_layout(int layout, const wdd::SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    switch (layout) {
+        case DD_LAYOUT_NODE: return wdd::launch_sweep_node<Real>(a, P, wg, s);
+        case DD_LAYOUT_PATCH: return wdd::launch_sweep_patch1<Real>(a, P, wg, s);
+        case DD_LAYOUT_STREAM: return wdd::launch_sweep_stream<Real>(a, P, wg, s);
+        default: return wdd::launch_sweep_patch<Real>(a, P, wg, s);
     }
-    HIPCHK(e);
-    if (timed) HIPCHK(hipEventRecord(h->ev1, s));
-    HIPCHK(hipMemcpyAsync(h->iters_host.data(), h->d_iters.p, sizeof(int) * h->L,
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (timed) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        h->st.sweep_seconds += ms * 1e-3;
-    }
+}
+
+// Fold one launch's WaveHoltz counts of this handle into its stats.
+void account_sweep(dd_handle* h, const int* iters, double seconds, int prec) {
+    h->st.sweep_seconds += seconds;
     h->st.sweeps += 1;
     if (prec == DD_FP64 && h->opt.precision == DD_FP32) h->st.fp64_sweeps += 1;
     for (int64_t l = 0; l < h->L; ++l) {
-        const int it = h->iters_host[l];
+        const int it = iters[l];
+        h->iters_host[l] = it;
+        h->last_iters[l] = it;
         h->st.wh_iters_total += it;
         h->st.wh_iters_max = std::max(h->st.wh_iters_max, it);
         h->st.dof_updates += (double)h->nloc * (h->nt[l] - 1) * it;
     }
+}
+
+int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
+                int prec, double tau, int max_wh);
+
+// One sweep launch of this handle alone: g_out = sweep(g_in, src), u =
+// subdomain solutions.  In a shared store the vectors pass through the
+// handle's range of the exchange buffers.
+int run_sweep_direct(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
+                     bool timed, int prec, double tau, int max_wh) {
+    hipStream_t s = h->stream;
+    Store* S = h->store;
+    const double2* gi = g_in;
+    double2* go = g_out;
+    if (S->shared) {
+        HIPCHK(hipMemcpyAsync(S->d_gin.p + h->if_base, g_in, sizeof(double2) * h->n_if,
+                              hipMemcpyDeviceToDevice, s));
+        gi = S->d_gin.p;
+        go = S->d_gout.p;
+    }
+    if (timed) HIPCHK(hipEventRecord(h->ev0, s));
+    hipError_t e;
+    if (prec == DD_FP32)
+        e = launch_layout<float>(h->layout, make_args<float>(h, gi, go, src, with_f, tau, max_wh),
+                                 h->P, h->wg, s);
+    else
+        e = launch_layout<double>(h->layout, make_args<double>(h, gi, go, src, with_f, tau, max_wh),
+                                  h->P, h->wg, s);
+    HIPCHK(e);
+    if (timed) HIPCHK(hipEventRecord(h->ev1, s));
+    if (S->shared)
+        HIPCHK(hipMemcpyAsync(g_out, S->d_gout.p + h->if_base, sizeof(double2) * h->n_if,
+                              hipMemcpyDeviceToDevice, s));
+    std::vector<int> its(h->L);
+    HIPCHK(hipMemcpyAsync(its.data(), S->d_iters.p + h->item_base, sizeof(int) * h->L,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    if (timed) HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    account_sweep(h, its.data(), ms * 1e-3, prec);
+    return DD_OK;
+}
+
+int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
+              bool timed, int prec, double tau, int max_wh) {
+    if (h->batched) return sched_sweep(h, g_in, g_out, src, with_f, prec, tau, max_wh);
+    return run_sweep_direct(h, g_in, g_out, src, with_f, timed, prec, tau, max_wh);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: the sweeps of several problems of one store in one
+// launch per launch configuration, longest-first
+// ---------------------------------------------------------------------------
+
+// LDS of a launch of this handle's layout at another workgroup size and
+// table length (a group of problems shares one launch configuration).
+size_t lds_for(const dd_handle* h, int prec, int wg, int nt_max) {
+    const size_t rs = prec_size(prec);
+    switch (h->layout) {
+        case DD_LAYOUT_NODE: return wdd::node_lds_bytes(h->nxl, h->nyl, nt_max, rs);
+        case DD_LAYOUT_STREAM: return wdd::stream_lds_bytes(h->P, nt_max, rs);
+        case DD_LAYOUT_PATCH_XCHG: return wdd::patch_lds_bytes(h->mx, h->my, h->P, nt_max, rs);
+        default: return wdd::patch1_lds_bytes(h->mx, h->my, h->P, wg, nt_max, rs);
+    }
+}
+
+// Workgroup-size class of a layout's kernel template (items of one launch
+// must share it; blockDim is the largest need in the class).
+int wg_class(int layout, int wg) {
+    if (layout == DD_LAYOUT_PATCH || layout == DD_LAYOUT_PATCH_XCHG) return wg <= 256 ? 256 : 512;
+    return 1024;
+}
+
+// Estimated cost of a subdomain: DOF-updates of its last sweep.
+double item_cost(const dd_handle* h, int64_t l) {
+    return (double)h->nloc * (h->nt[l] - 1) * std::max(1, h->last_iters[l]);
+}
+
+// One batched launch over the requests' subdomains.  Requests are grouped
+// by launch configuration (precision, degree, layout, workgroup class,
+// source); each group is one launch whose work list is sorted by cost,
+// longest first (the hardware dispatches workgroups in order, so the list
+// is the schedule).  Groups run concurrently on the store's group streams.
+int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, double* ms_out = nullptr,
+                 int* groups_out = nullptr) {
+    HIPCHK(hipSetDevice(S->dev));
+    struct Item {
+        double cost;
+        int r;
+        int64_t l;
+    };
+    struct Group {
+        std::vector<Item> items;
+        int prec = 0, P = 0, layout = 0, wg = 0, nt_max = 0;
+        double src = 0.0;
+        size_t lds = 0;
+        int64_t off = 0;
+    };
+    std::map<std::tuple<int, int, int, int, double, const void*>, Group> groups;
+    for (int r = 0; r < (int)reqs.size(); ++r) {
+        const SweepReq* q = reqs[r];
+        const dd_handle* h = q->h;
+        const double src = (q->with_f && q->src != 0.0) ? q->src : 0.0;
+        auto key = std::make_tuple(q->prec, h->P, h->layout, wg_class(h->layout, h->wg), src,
+                                   (const void*)nullptr);
+        Group& g = groups[key];
+        const int wg = std::max(g.wg, h->wg), ntm = std::max(g.nt_max, h->nt_max);
+        bool fits = lds_for(h, q->prec, wg, ntm) <= kLdsLimit;
+        for (const Item& it : g.items) fits = fits && lds_for(reqs[it.r]->h, q->prec, wg, ntm) <= kLdsLimit;
+        Group& gg = fits ? g : groups[std::make_tuple(q->prec, h->P, h->layout,
+                                                      wg_class(h->layout, h->wg), src, (const void*)h)];
+        gg.prec = q->prec;
+        gg.P = h->P;
+        gg.layout = h->layout;
+        gg.src = src;
+        gg.wg = std::max(gg.wg, h->wg);
+        gg.nt_max = std::max(gg.nt_max, h->nt_max);
+        for (int64_t l = 0; l < h->L; ++l) gg.items.push_back({item_cost(h, l), r, l});
+    }
+    int64_t total = 0;
+    for (const auto& kv : groups) total += (int64_t)kv.second.items.size();
+    if (total > S->cap_item) return fail(DD_EINVAL, "batched work list exceeds the store");
+    total = 0;
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        std::stable_sort(g.items.begin(), g.items.end(),
+                         [](const Item& a, const Item& b) { return a.cost > b.cost; });
+        g.off = total;
+        for (size_t i = 0; i < g.items.size(); ++i) {
+            const Item& it = g.items[i];
+            const SweepReq* q = reqs[it.r];
+            wdd::SubDesc d = q->h->desc[it.l];
+            d.max_wh = q->max_wh;
+            d.tau = q->tau;
+            S->h_work[total + (int64_t)i] = d;
+        }
+        for (const Item& it : g.items)
+            g.lds = std::max(g.lds, lds_for(reqs[it.r]->h, g.prec, g.wg, g.nt_max));
+        total += (int64_t)g.items.size();
+    }
+    hipStream_t s = S->stream;
+    HIPCHK(hipEventRecord(S->ev0, s));
+    HIPCHK(hipMemcpyAsync(S->d_work.p, S->h_work, sizeof(wdd::SubDesc) * total,
+                          hipMemcpyHostToDevice, s));
+    for (const SweepReq* q : reqs)
+        HIPCHK(hipMemcpyAsync(S->d_gin.p + q->h->if_base, q->g_in, sizeof(double2) * q->h->n_if,
+                              hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipEventRecord(S->ev_in, s));
+    const double(*K1)[wdd::kMaxP + 1][wdd::kMaxP + 1] = reqs[0]->h->K1all;
+    int gi = 0;
+    bool used[Store::kGroupStreams] = {};
+    for (auto& kv : groups) {
+        Group& g = kv.second;
+        if (g.items.empty()) continue;
+        const int k = gi++ % Store::kGroupStreams;
+        hipStream_t gs = S->gs[k];
+        if (!used[k]) HIPCHK(hipStreamWaitEvent(gs, S->ev_in, 0));
+        used[k] = true;
+        const bool wf = g.src != 0.0;
+        hipError_t e;
+        if (g.prec == DD_FP32) {
+            auto a = store_args<float>(S, S->d_gin.p, S->d_gout.p, g.src, wf, 0.0, 1, K1);
+            a.desc = S->d_work.p + g.off;
+            a.n_items = (int)g.items.size();
+            a.wh_iters = S->d_work_iters.p + g.off;
+            a.lds_bytes = g.lds;
+            a.nt_max = g.nt_max;
+            e = launch_layout<float>(g.layout, a, g.P, g.wg, gs);
+        } else {
+            auto a = store_args<double>(S, S->d_gin.p, S->d_gout.p, g.src, wf, 0.0, 1, K1);
+            a.desc = S->d_work.p + g.off;
+            a.n_items = (int)g.items.size();
+            a.wh_iters = S->d_work_iters.p + g.off;
+            a.lds_bytes = g.lds;
+            a.nt_max = g.nt_max;
+            e = launch_layout<double>(g.layout, a, g.P, g.wg, gs);
+        }
+        HIPCHK(e);
+    }
+    for (int k = 0; k < Store::kGroupStreams; ++k) {
+        if (!used[k]) continue;
+        HIPCHK(hipEventRecord(S->gev[k], S->gs[k]));
+        HIPCHK(hipStreamWaitEvent(s, S->gev[k], 0));
+    }
+    HIPCHK(hipEventRecord(S->ev1, s));
+    for (const SweepReq* q : reqs)
+        HIPCHK(hipMemcpyAsync(q->g_out, S->d_gout.p + q->h->if_base, sizeof(double2) * q->h->n_if,
+                              hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(S->h_work_iters, S->d_work_iters.p, sizeof(int) * total,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+    std::vector<std::vector<int>> its(reqs.size());
+    for (size_t r = 0; r < reqs.size(); ++r) its[r].assign(reqs[r]->h->L, 0);
+    for (auto& kv : groups) {
+        const Group& g = kv.second;
+        for (size_t i = 0; i < g.items.size(); ++i)
+            its[g.items[i].r][g.items[i].l] = S->h_work_iters[g.off + (int64_t)i];
+    }
+    for (size_t r = 0; r < reqs.size(); ++r)
+        account_sweep(reqs[r]->h, its[r].data(), ms * 1e-3, reqs[r]->prec);
+    S->sched.launches += 1;
+    if (ms_out) *ms_out = ms;
+    if (groups_out) *groups_out = gi;
+    return DD_OK;
+}
+
+void sched_maybe_launch(Store* S, std::unique_lock<std::mutex>& lk) {
+    Sched& Q = S->sched;
+    while (!Q.launching && Q.active > 0 && (int)Q.pending.size() >= Q.active) {
+        std::vector<SweepReq*> batch;
+        batch.swap(Q.pending);
+        Q.launching = true;
+        lk.unlock();
+        const int rc = launch_batch(S, batch);
+        const std::string msg = rc == DD_OK ? std::string() : g_err;
+        lk.lock();
+        for (SweepReq* r : batch) {
+            r->rc = rc;
+            r->done = true;
+        }
+        Q.err = msg;
+        Q.launching = false;
+        Q.cv.notify_all();
+    }
+}
+
+void sched_join(Store* S) {
+    std::lock_guard<std::mutex> lk(S->sched.mu);
+    S->sched.active += 1;
+}
+
+void sched_leave(Store* S) {
+    std::unique_lock<std::mutex> lk(S->sched.mu);
+    S->sched.active -= 1;
+    sched_maybe_launch(S, lk);
+}
+
+// A sweep of a batched handle: post it and wait for the launch that
+// carries it (launched by whichever problem posts last).
+int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
+                int prec, double tau, int max_wh) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    Store* S = h->store;
+    Sched& Q = S->sched;
+    SweepReq req{h, g_in, g_out, src, with_f, prec, tau, max_wh};
+    std::unique_lock<std::mutex> lk(Q.mu);
+    Q.pending.push_back(&req);
+    sched_maybe_launch(S, lk);
+    Q.cv.wait(lk, [&] { return req.done; });
+    if (req.rc != DD_OK) return fail(req.rc, "batched sweep: %s", Q.err.c_str());
     return DD_OK;
 }
 
@@ -621,16 +990,20 @@ int check_finite(const double* x, int64_t n, const char* name) {
 
 int stage_source(dd_handle* h, const double* d_fre, const double* d_fim) {
     const int64_t n = h->L * h->nloc;
+    Store* S = h->store;
     for (int prec : {DD_FP64, DD_FP32}) {
-        const dd_handle::PrecBuf& B = h->pb[prec_index(prec)];
+        const Store::PrecBuf& B = S->pb[prec_index(prec)];
         if (!B.present) continue;
         const size_t rs = prec_size(prec);
-        char* F = B.F.p;
-        HIPCHK(wdd::gather_source(d_fre, d_fim, h->d_gidx.p, h->d_area.p, n, F, F + rs * n,
+        char* F = B.F.p + rs * h->node_base;
+        HIPCHK(wdd::gather_source(d_fre, d_fim, S->d_gidx.p + h->node_base,
+                                  S->d_area.p + h->node_base, n, F, F + rs * S->cap_node,
                                   prec == DD_FP32, h->stream));
     }
     return DD_OK;
 }
+
+double2* u_dev(const dd_handle* h) { return h->store->d_u.p + h->node_base; }
 
 int ensure_staging(dd_handle* h) {
     if (!h->d_fre.p) {
@@ -689,59 +1062,20 @@ int autotune_layout(dd_handle* h) {
     return DD_OK;
 }
 
-}  // namespace
 
-// ===========================================================================
-// C ABI
-// ===========================================================================
-extern "C" {
+// Host-side arrays of one problem, computed before any device work.
+struct HostArrays {
+    std::vector<double> alpha, betaX, betaY, beta, area, w1d, kap, kaph, cs, sn, kside;
+    std::vector<double> wxg, wyg, Mg, Hg;
+    std::vector<int> gidx, is_iface;
+    std::vector<int64_t> trace_idx;
+};
 
-const char* dd_last_error(void) { return g_err.c_str(); }
-
-int dd_default_options(dd_options* o) {
-    if (!o) return fail(DD_EINVAL, "null options");
-    o->precision = DD_FP64;
-    o->layout = DD_LAYOUT_AUTO;
-    o->tau_in = 1e-12;
-    o->max_wh = 100;
-    o->outer = DD_OUTER_GMRES;
-    o->restart = 50;
-    o->nt_override = 0;
-    o->cfl = 0.9;
-    o->refine = 4;
-    o->relax = 0.0;
-    return DD_OK;
-}
-
-void dd_destroy(dd_handle* h) {
-    if (!h) return;
-    (void)hipSetDevice(h->dev);
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    h->d_desc.free();
-    for (auto& B : h->pb) {
-        B.coef.free();
-        B.tab.free();
-        B.F.free();
-    }
-    h->d_D.free(); h->d_res.free();
-    h->d_w1d.free(); h->d_kside.free(); h->d_area.free();
-    h->d_gidx.free(); h->d_iters.free(); h->d_is_iface.free(); h->d_trace_idx.free();
-    h->d_u.free(); h->d_V.free(); h->d_G.free(); h->d_h.free(); h->d_tmp.free(); h->d_g0.free();
-    h->d_r.free(); h->d_coefs.free();
-    h->d_fre.free(); h->d_fim.free(); h->d_gre.free(); h->d_gim.free(); h->d_ure.free();
-    h->d_uim.free(); h->d_wxg.free(); h->d_wyg.free(); h->d_Mg.free(); h->d_Hg.free();
-    h->d_work.free();
-    wdd::blas_free(h->blas);
-    if (h->ev0) (void)hipEventDestroy(h->ev0);
-    if (h->ev1) (void)hipEventDestroy(h->ev1);
-    if (h->stream) (void)hipStreamDestroy(h->stream);
-    delete h;
-}
-
-int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wavespeed,
-             double omega, const dd_partition* part, const dd_options* opt) {
-    if (!out) return fail(DD_EINVAL, "null output handle pointer");
-    *out = nullptr;
+// Validate a problem and compute everything the device needs (Sec. IV
+// lumped operators, Sec. V leapfrog coefficients and filter tables, the
+// time-step rule, the layout).  Descriptors carry problem-local offsets.
+int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespeed, double omega,
+            const dd_partition* part, const dd_options* opt, HostArrays& ha) {
     if (!mesh || !part || !wavespeed) return fail(DD_EINVAL, "null mesh, partition or wavespeed");
     if (degree < 1 || degree > wdd::kMaxP)
         return fail(DD_EINVAL, "degree %d not in [1, %d]", degree, wdd::kMaxP);
@@ -759,7 +1093,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     else
         dd_default_options(&o);
     if (o.precision != DD_FP64 && o.precision != DD_FP32) return fail(DD_EINVAL, "bad precision");
-    if (o.layout < DD_LAYOUT_AUTO || o.layout > DD_LAYOUT_PATCH_XCHG) return fail(DD_EINVAL, "bad layout");
+    if (o.layout < DD_LAYOUT_AUTO || o.layout > DD_LAYOUT_STREAM) return fail(DD_EINVAL, "bad layout");
     if (o.max_wh < 1) return fail(DD_EINVAL, "max_wh must be >= 1");
     if (o.outer != DD_OUTER_GMRES && o.outer != DD_OUTER_FIXED)
         return fail(DD_EINVAL, "bad outer method");
@@ -779,7 +1113,6 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
                         wavespeed[i]);
     const int mx = mesh->nx / part->sx, my = mesh->ny / part->sy;
     const int nxl = mx * P + 1, nyl = my * P + 1;
-    dd_handle* h = new dd_handle();
     h->mesh = *mesh;
     h->P = P;
     h->omega = omega;
@@ -848,34 +1181,19 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
         why = "patch layout needs <= 512 threads (element patches) per subdomain and its LDS";
     else if (lay == DD_LAYOUT_PATCH_XCHG && !xchg_ok)
         why = "patch layout needs <= 512 threads (element patches) per subdomain";
-    else if (!node_ok && !patch_ok && !xchg_ok)
-        why = "subdomain too large for the on-chip layouts";
+    else if (lay == DD_LAYOUT_STREAM && !layout_fits(h, DD_LAYOUT_STREAM))
+        why = "streaming layout tables exceed the LDS (N_t too large)";
+    else if (!node_ok && !patch_ok && !xchg_ok && !layout_fits(h, DD_LAYOUT_STREAM))
+        why = "no layout fits (N_t too large)";
     if (why) {
-        delete h;
         return fail(DD_EINVAL, "%s (subdomain %dx%d elements, P=%d)", why, mx, my, P);
     }
-    if (lay == DD_LAYOUT_AUTO) lay = patch_ok ? DD_LAYOUT_PATCH : xchg_ok ? DD_LAYOUT_PATCH_XCHG : DD_LAYOUT_NODE;
+    if (lay == DD_LAYOUT_AUTO)
+        lay = patch_ok ? DD_LAYOUT_PATCH
+              : xchg_ok ? DD_LAYOUT_PATCH_XCHG
+              : node_ok ? DD_LAYOUT_NODE
+                        : DD_LAYOUT_STREAM;
     layout_config(h, lay);
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-        delete h;
-        return fail(DD_ENODEV, "no HIP device");
-    }
-    (void)hipGetDevice(&h->dev);
-
-    auto bail = [&](int code) {
-        dd_destroy(h);
-        return code;
-    };
-#define SCHK(expr)                                                                              \
-    do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
-            return bail(fail(e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP, "%s: %s", #expr,  \
-                             hipGetErrorString(e_)));                                           \
-    } while (0)
-
-
     // physical lumped 1D weights of a subdomain (the same for all)
     std::vector<double> w1d(nxl + nyl);
     for (int il = 0; il < nxl; ++il) w1d[il] = 0.5 * h->hx * wref(g, il, mx);
@@ -939,6 +1257,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
         d.two_over_nt = 2.0 / n;
         d.sx_ref = 2.0 / h->hx;
         d.sy_ref = 2.0 / h->hy;
+        d.ws_off = l * 2 * wdd::stream_pad_nodes(nxl, nyl);
     }
     // interface bookkeeping: omega/c per slot, outer-trace index of physical
     // slots, interface flags
@@ -984,85 +1303,355 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
             Hg[gi] = Hs / cc;
         }
 
-    // device allocation and upload
-    SCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-    SCHK(hipEventCreate(&h->ev0));
-    SCHK(hipEventCreate(&h->ev1));
-    const size_t rs = real_size(h);
-    SCHK(h->d_desc.alloc(L));
-    h->pb[0].present = true;
-    h->pb[1].present = o.precision == DD_FP32;
-    for (auto& B : h->pb) {
-        if (!B.present) continue;
-        const size_t bs = (&B == &h->pb[1]) ? 4 : 8;
-        SCHK(B.coef.alloc(4 * bs * nn));
-        SCHK(B.tab.alloc(4 * bs * h->tab_len));
-        SCHK(B.F.alloc(2 * bs * nn));
-    }
-    SCHK(h->d_D.alloc(h->n_if));
-    SCHK(h->d_res.alloc(h->n_if));
-    SCHK(h->d_w1d.alloc(nxl + nyl));
-    SCHK(h->d_kside.alloc(h->n_if));
-    SCHK(h->d_area.alloc(nn));
-    SCHK(h->d_gidx.alloc(nn));
-    SCHK(h->d_iters.alloc(L));
-    SCHK(h->d_is_iface.alloc(h->n_if));
-    SCHK(h->d_trace_idx.alloc(h->n_if));
-    SCHK(h->d_u.alloc(nn));
-    h->ld = ((h->n_if + 63) / 64) * 64;
-    SCHK(h->d_V.alloc((size_t)(o.restart + 1) * h->ld));
-    SCHK(h->d_G.alloc(h->n_if));
-    SCHK(h->d_h.alloc(h->n_if));
-    SCHK(h->d_tmp.alloc(h->n_if));
-    SCHK(h->d_g0.alloc(h->n_if));
-    SCHK(h->d_r.alloc(h->n_if));
-    SCHK(h->d_coefs.alloc(o.restart + 1));
-    SCHK(h->d_wxg.alloc(Nx));
-    SCHK(h->d_wyg.alloc(Ny));
-    SCHK(h->d_Mg.alloc(N));
-    SCHK(h->d_Hg.alloc(N));
-    SCHK(wdd::blas_init(h->blas, o.restart + 2, h->stream));
-    h->iters_host.assign(L, 0);
+    ha.alpha = std::move(alpha);
+    ha.betaX = std::move(betaX);
+    ha.betaY = std::move(betaY);
+    ha.beta = std::move(beta);
+    ha.area = std::move(area);
+    ha.gidx = std::move(gidx);
+    ha.w1d = std::move(w1d);
+    ha.kap = std::move(kap);
+    ha.kaph = std::move(kaph);
+    ha.cs = std::move(cs);
+    ha.sn = std::move(sn);
+    ha.kside = std::move(kside);
+    ha.trace_idx = std::move(trace_idx);
+    ha.is_iface = std::move(is_iface);
+    ha.wxg = std::move(wxg);
+    ha.wyg = std::move(wyg);
+    ha.Mg = std::move(Mg);
+    ha.Hg = std::move(Hg);
+    return DD_OK;
+}
 
-    auto up_real = [&](char* dst, const std::vector<double>& v, size_t bs) -> hipError_t {
+void store_destroy(Store* S) {
+    if (!S) return;
+    (void)hipSetDevice(S->dev);
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (auto& B : S->pb) {
+        B.coef.free();
+        B.tab.free();
+        B.F.free();
+    }
+    S->d_desc.free();
+    S->d_w1d.free(); S->d_kside.free(); S->d_area.free();
+    S->d_gidx.free(); S->d_iters.free(); S->d_is_iface.free(); S->d_trace_idx.free();
+    S->d_u.free(); S->d_wsp.free(); S->d_wss.free();
+    S->d_gin.free(); S->d_gout.free(); S->d_work.free(); S->d_work_iters.free();
+    if (S->h_work) (void)hipHostFree(S->h_work);
+    if (S->h_work_iters) (void)hipHostFree(S->h_work_iters);
+    for (int i = 0; i < Store::kGroupStreams; ++i) {
+        if (S->gev[i]) (void)hipEventDestroy(S->gev[i]);
+        if (S->gs[i]) (void)hipStreamDestroy(S->gs[i]);
+    }
+    if (S->ev_in) (void)hipEventDestroy(S->ev_in);
+    if (S->ev0) (void)hipEventDestroy(S->ev0);
+    if (S->ev1) (void)hipEventDestroy(S->ev1);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+}
+
+// Allocate a store with the given capacities (entries per index space).
+int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int64_t ct,
+                 int64_t cw, int64_t cwsp, bool fp32, bool shared) {
+    *out = nullptr;
+    Store* S = new Store();
+    S->dev = dev;
+    S->shared = shared;
+    S->align = shared ? 64 : 1;
+    S->cap_node = cn;
+    S->cap_if = ci;
+    S->cap_item = cit;
+    S->cap_tab = ct;
+    S->cap_w1d = cw;
+    S->cap_wsp = cwsp;
+    S->a_node.init(cn);
+    S->a_if.init(ci);
+    S->a_item.init(cit);
+    S->a_tab.init(ct);
+    S->a_w1d.init(cw);
+    S->a_wsp.init(cwsp);
+    S->pb[0].present = true;
+    S->pb[1].present = fp32;
+#define STCHK(expr)                                                                              \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            const int c_ = fail(e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP, "%s: %s", #expr, \
+                                hipGetErrorString(e_));                                          \
+            store_destroy(S);                                                                    \
+            return c_;                                                                           \
+        }                                                                                        \
+    } while (0)
+    STCHK(hipSetDevice(dev));
+    size_t bytes = 0;
+    for (int k = 0; k < 2; ++k) {
+        Store::PrecBuf& B = S->pb[k];
+        if (!B.present) continue;
+        const size_t bs = k == 1 ? 4 : 8;
+        STCHK(B.coef.alloc(4 * bs * cn));
+        STCHK(B.tab.alloc(4 * bs * ct));
+        STCHK(B.F.alloc(2 * bs * cn));
+        bytes += bs * (6 * cn + 4 * ct);
+    }
+    STCHK(S->d_desc.alloc(cit));
+    STCHK(S->d_w1d.alloc(cw));
+    STCHK(S->d_kside.alloc(ci));
+    STCHK(S->d_area.alloc(cn));
+    STCHK(S->d_gidx.alloc(cn));
+    STCHK(S->d_iters.alloc(cit));
+    STCHK(S->d_is_iface.alloc(ci));
+    STCHK(S->d_trace_idx.alloc(ci));
+    STCHK(S->d_u.alloc(cn));
+    bytes += cit * (sizeof(wdd::SubDesc) + 4) + cw * 8 + ci * 20 + cn * 28;
+    if (cwsp > 0) {
+        STCHK(S->d_wsp.alloc(cwsp));
+        STCHK(S->d_wss.alloc(5 * cn));
+        bytes += 8 * (cwsp + 5 * cn);
+    }
+    STCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+    STCHK(hipEventCreate(&S->ev0));
+    STCHK(hipEventCreate(&S->ev1));
+    if (shared) {
+        STCHK(S->d_gin.alloc(ci));
+        STCHK(S->d_gout.alloc(ci));
+        STCHK(S->d_work.alloc(cit));
+        STCHK(S->d_work_iters.alloc(cit));
+        STCHK(hipHostMalloc((void**)&S->h_work, sizeof(wdd::SubDesc) * std::max<int64_t>(cit, 1)));
+        STCHK(hipHostMalloc((void**)&S->h_work_iters, sizeof(int) * std::max<int64_t>(cit, 1)));
+        STCHK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+        for (int i = 0; i < Store::kGroupStreams; ++i) {
+            STCHK(hipStreamCreateWithFlags(&S->gs[i], hipStreamNonBlocking));
+            STCHK(hipEventCreateWithFlags(&S->gev[i], hipEventDisableTiming));
+        }
+        bytes += ci * 32 + cit * (sizeof(wdd::SubDesc) + 4);
+    }
+#undef STCHK
+    S->bytes = bytes;
+    *out = S;
+    return DD_OK;
+}
+
+// Device bytes a placed problem holds outside the store.
+size_t problem_own_bytes(const dd_handle* h) {
+    const int64_t ld = ((h->n_if + 63) / 64) * 64;
+    return sizeof(double2) * ((size_t)(h->opt.restart + 1) * ld + 8 * (size_t)h->n_if +
+                              (h->opt.restart + 1)) +
+           8 * ((size_t)h->Nx + h->Ny + 2 * (size_t)h->N) +
+           sizeof(double2) * (size_t)(h->opt.restart + 2) * 1024;
+}
+
+// Range lengths of a problem in a store.
+void problem_ranges(dd_handle* h, int64_t align) {
+    auto rnd = [&](int64_t n) { return (n + align - 1) / align * align; };
+    h->node_len = rnd(h->L * h->nloc);
+    h->if_len = rnd(h->n_if);
+    h->item_len = h->L;
+    h->w1d_len = h->nxl + h->nyl;
+    h->wsp_len = h->layout == DD_LAYOUT_STREAM ? h->L * 2 * wdd::stream_pad_nodes(h->nxl, h->nyl) : 0;
+}
+
+void unplace(dd_handle* h) {
+    (void)hipSetDevice(h->dev);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    h->d_V.free(); h->d_G.free(); h->d_h.free(); h->d_tmp.free(); h->d_g0.free();
+    h->d_r.free(); h->d_coefs.free(); h->d_D.free(); h->d_res.free();
+    h->d_fre.free(); h->d_fim.free(); h->d_gre.free(); h->d_gim.free(); h->d_ure.free();
+    h->d_uim.free(); h->d_wxg.free(); h->d_wyg.free(); h->d_Mg.free(); h->d_Hg.free();
+    h->d_work.free();
+    wdd::blas_free(h->blas);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    h->ev0 = h->ev1 = nullptr;
+    h->stream = nullptr;
+    if (h->placed && h->store) {
+        Store* S = h->store;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->a_node.release(h->node_base, h->node_len);
+        S->a_if.release(h->if_base, h->if_len);
+        S->a_item.release(h->item_base, h->item_len);
+        S->a_tab.release(h->tab_base, h->tab_len);
+        S->a_w1d.release(h->w1d_base, h->w1d_len);
+        S->a_wsp.release(h->wsp_base, h->wsp_len);
+        h->placed = false;
+    }
+}
+
+// Reserve the problem's ranges in the store (DD_ENOMEM if any is full).
+int reserve(dd_handle* h, Store* S) {
+    problem_ranges(h, S->align);
+    std::lock_guard<std::mutex> lk(S->mu);
+    int64_t* base[6] = {&h->node_base, &h->if_base, &h->item_base, &h->tab_base, &h->w1d_base,
+                        &h->wsp_base};
+    const int64_t len[6] = {h->node_len, h->if_len, h->item_len, h->tab_len, h->w1d_len, h->wsp_len};
+    RangeAlloc* ra[6] = {&S->a_node, &S->a_if, &S->a_item, &S->a_tab, &S->a_w1d, &S->a_wsp};
+    for (int k = 0; k < 6; ++k) {
+        *base[k] = ra[k]->alloc(len[k]);
+        if (*base[k] < 0) {
+            for (int q = 0; q < k; ++q) ra[q]->release(*base[q], len[q]);
+            return fail(DD_ENOMEM, "device store full");
+        }
+    }
+    h->store = S;
+    h->dev = S->dev;
+    h->placed = true;
+    return DD_OK;
+}
+
+// Upload a reserved problem into its store ranges and allocate its outer
+// iteration vectors.  On failure the caller unplaces.
+int upload(dd_handle* h, const HostArrays& ha) {
+    Store* S = h->store;
+    HIPCHK(hipSetDevice(S->dev));
+    const int64_t L = h->L, nn = L * h->nloc;
+    for (auto& d : h->desc) {
+        d.node_off += h->node_base;
+        d.w_off = h->w1d_base;
+        d.if_off += h->if_base;
+        for (int s = 0; s < 4; ++s)
+            if (d.nbr_off[s] >= 0) d.nbr_off[s] += h->if_base;
+        d.toff += (int)h->tab_base;
+        d.ws_off += h->wsp_base;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&h->ev0));
+    HIPCHK(hipEventCreate(&h->ev1));
+    auto up_real = [&](char* base, int64_t stride, int k, int64_t off, const std::vector<double>& v,
+                       size_t bs) -> hipError_t {
+        char* dst = base + bs * ((size_t)k * stride + off);
         if (bs == 8) return hipMemcpy(dst, v.data(), 8 * v.size(), hipMemcpyHostToDevice);
         std::vector<float> f(v.begin(), v.end());
         return hipMemcpy(dst, f.data(), 4 * f.size(), hipMemcpyHostToDevice);
     };
-    SCHK(hipMemcpy(h->d_desc.p, h->desc.data(), sizeof(wdd::SubDesc) * L, hipMemcpyHostToDevice));
-    for (auto& B : h->pb) {
+    HIPCHK(hipMemcpy(S->d_desc.p + h->item_base, h->desc.data(), sizeof(wdd::SubDesc) * L,
+                     hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) {
+        Store::PrecBuf& B = S->pb[k];
         if (!B.present) continue;
-        const size_t bs = (&B == &h->pb[1]) ? 4 : 8;
-        SCHK(up_real(B.coef.p, alpha, bs));
-        SCHK(up_real(B.coef.p + bs * nn, betaX, bs));
-        SCHK(up_real(B.coef.p + 2 * bs * nn, betaY, bs));
-        SCHK(up_real(B.coef.p + 3 * bs * nn, beta, bs));
-        SCHK(up_real(B.tab.p, kap, bs));
-        SCHK(up_real(B.tab.p + bs * h->tab_len, kaph, bs));
-        SCHK(up_real(B.tab.p + 2 * bs * h->tab_len, cs, bs));
-        SCHK(up_real(B.tab.p + 3 * bs * h->tab_len, sn, bs));
-        SCHK(hipMemset(B.F.p, 0, 2 * bs * nn));
+        const size_t bs = k == 1 ? 4 : 8;
+        HIPCHK(up_real(B.coef.p, S->cap_node, 0, h->node_base, ha.alpha, bs));
+        HIPCHK(up_real(B.coef.p, S->cap_node, 1, h->node_base, ha.betaX, bs));
+        HIPCHK(up_real(B.coef.p, S->cap_node, 2, h->node_base, ha.betaY, bs));
+        HIPCHK(up_real(B.coef.p, S->cap_node, 3, h->node_base, ha.beta, bs));
+        HIPCHK(up_real(B.tab.p, S->cap_tab, 0, h->tab_base, ha.kap, bs));
+        HIPCHK(up_real(B.tab.p, S->cap_tab, 1, h->tab_base, ha.kaph, bs));
+        HIPCHK(up_real(B.tab.p, S->cap_tab, 2, h->tab_base, ha.cs, bs));
+        HIPCHK(up_real(B.tab.p, S->cap_tab, 3, h->tab_base, ha.sn, bs));
+        for (int q = 0; q < 2; ++q)
+            HIPCHK(hipMemset(B.F.p + bs * ((size_t)q * S->cap_node + h->node_base), 0, bs * nn));
     }
-    SCHK(hipMemcpy(h->d_w1d.p, w1d.data(), 8 * w1d.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_kside.p, kside.data(), 8 * kside.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_area.p, area.data(), 8 * area.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_gidx.p, gidx.data(), 4 * gidx.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_is_iface.p, is_iface.data(), 4 * is_iface.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_trace_idx.p, trace_idx.data(), 8 * trace_idx.size(), hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_wxg.p, wxg.data(), 8 * (size_t)Nx, hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_wyg.p, wyg.data(), 8 * (size_t)Ny, hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_Mg.p, Mg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
-    SCHK(hipMemcpy(h->d_Hg.p, Hg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
-    SCHK(hipMemset(h->d_u.p, 0, sizeof(double2) * nn));
-    SCHK(hipMemset(h->d_G.p, 0, sizeof(double2) * h->n_if));
-    SCHK(hipMemset(h->d_g0.p, 0, sizeof(double2) * h->n_if));
-#undef SCHK
-    if (o.layout == DD_LAYOUT_AUTO) {
-        const int rc = autotune_layout(h);
-        if (rc != DD_OK) {
-            dd_destroy(h);
-            return rc;
-        }
+    HIPCHK(hipMemcpy(S->d_w1d.p + h->w1d_base, ha.w1d.data(), 8 * ha.w1d.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_kside.p + h->if_base, ha.kside.data(), 8 * ha.kside.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_area.p + h->node_base, ha.area.data(), 8 * ha.area.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_gidx.p + h->node_base, ha.gidx.data(), 4 * ha.gidx.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_is_iface.p + h->if_base, ha.is_iface.data(), 4 * ha.is_iface.size(),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_trace_idx.p + h->if_base, ha.trace_idx.data(), 8 * ha.trace_idx.size(),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(S->d_u.p + h->node_base, 0, sizeof(double2) * nn));
+    if (h->wsp_len > 0) {
+        // the zero padding of the p grids is never written: clear once
+        HIPCHK(hipMemset(S->d_wsp.p + h->wsp_base, 0, sizeof(double) * h->wsp_len));
+    }
+    const int64_t Nx = h->Nx, Ny = h->Ny, N = h->N;
+    h->ld = ((h->n_if + 63) / 64) * 64;
+    HIPCHK(h->d_V.alloc((size_t)(h->opt.restart + 1) * h->ld));
+    HIPCHK(h->d_G.alloc(h->n_if));
+    HIPCHK(h->d_h.alloc(h->n_if));
+    HIPCHK(h->d_tmp.alloc(h->n_if));
+    HIPCHK(h->d_g0.alloc(h->n_if));
+    HIPCHK(h->d_r.alloc(h->n_if));
+    HIPCHK(h->d_D.alloc(h->n_if));
+    HIPCHK(h->d_res.alloc(h->n_if));
+    HIPCHK(h->d_coefs.alloc(h->opt.restart + 1));
+    HIPCHK(h->d_wxg.alloc(Nx));
+    HIPCHK(h->d_wyg.alloc(Ny));
+    HIPCHK(h->d_Mg.alloc(N));
+    HIPCHK(h->d_Hg.alloc(N));
+    HIPCHK(wdd::blas_init(h->blas, h->opt.restart + 2, h->stream));
+    h->own_bytes = problem_own_bytes(h);
+    h->iters_host.assign(L, 0);
+    h->last_iters.assign(L, 1);
+    HIPCHK(hipMemcpy(h->d_wxg.p, ha.wxg.data(), 8 * (size_t)Nx, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_wyg.p, ha.wyg.data(), 8 * (size_t)Ny, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_Mg.p, ha.Mg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_Hg.p, ha.Hg.data(), 8 * (size_t)N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(h->d_G.p, 0, sizeof(double2) * h->n_if));
+    HIPCHK(hipMemset(h->d_g0.p, 0, sizeof(double2) * h->n_if));
+    return DD_OK;
+}
+
+int device_present(int* dev) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(DD_ENODEV, "no HIP device");
+    (void)hipGetDevice(dev);
+    return DD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dd_last_error(void) { return g_err.c_str(); }
+
+int dd_default_options(dd_options* o) {
+    if (!o) return fail(DD_EINVAL, "null options");
+    o->precision = DD_FP64;
+    o->layout = DD_LAYOUT_AUTO;
+    o->tau_in = 1e-12;
+    o->max_wh = 100;
+    o->outer = DD_OUTER_GMRES;
+    o->restart = 50;
+    o->nt_override = 0;
+    o->cfl = 0.9;
+    o->refine = 4;
+    o->relax = 0.0;
+    return DD_OK;
+}
+
+void dd_destroy(dd_handle* h) {
+    if (!h) return;
+    Store* S = h->store;
+    const bool own = h->own_store;
+    unplace(h);
+    if (own) store_destroy(S);
+    delete h;
+}
+
+int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wavespeed,
+             double omega, const dd_partition* part, const dd_options* opt) {
+    if (!out) return fail(DD_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    dd_handle* h = new dd_handle();
+    HostArrays ha;
+    int rc = prepare(h, mesh, degree, wavespeed, omega, part, opt, ha);
+    int dev = 0;
+    if (rc == DD_OK) rc = device_present(&dev);
+    if (rc != DD_OK) {
+        delete h;
+        return rc;
+    }
+    problem_ranges(h, 1);
+    Store* S = nullptr;
+    rc = store_create(&S, dev, h->node_len, h->if_len, h->item_len, h->tab_len, h->w1d_len,
+                      h->wsp_len, h->opt.precision == DD_FP32, false);
+    if (rc != DD_OK) {
+        delete h;
+        return rc;
+    }
+    h->own_store = true;
+    h->store = S;
+    rc = reserve(h, S);
+    if (rc == DD_OK) rc = upload(h, ha);
+    if (rc == DD_OK && h->opt.layout == DD_LAYOUT_AUTO && h->layout != DD_LAYOUT_STREAM)
+        rc = autotune_layout(h);
+    if (rc != DD_OK) {
+        dd_destroy(h);
+        return rc;
     }
     *out = h;
     return DD_OK;
@@ -1107,6 +1696,30 @@ int dd_time_steps(const dd_handle* h, int* nt) {
     return DD_OK;
 }
 
+int dd_mesh_coords(const dd_mesh* mesh, int degree, double* x, double* y) {
+    if (!mesh || !x || !y) return fail(DD_EINVAL, "null argument");
+    if (degree < 1 || degree > wdd::kMaxP)
+        return fail(DD_EINVAL, "degree %d not in [1, %d]", degree, wdd::kMaxP);
+    if (mesh->nx < 1 || mesh->ny < 1) return fail(DD_EINVAL, "empty mesh");
+    if (!(mesh->x1 > mesh->x0) || !(mesh->y1 > mesh->y0)) return fail(DD_EINVAL, "degenerate rectangle");
+    const int P = degree, Nx = mesh->nx * P + 1, Ny = mesh->ny * P + 1;
+    const Gll g = make_gll(P);
+    const double hx = (mesh->x1 - mesh->x0) / mesh->nx, hy = (mesh->y1 - mesh->y0) / mesh->ny;
+    std::vector<double> xs(Nx), ys(Ny);
+    for (int e = 0; e < mesh->nx; ++e)
+        for (int a = 0; a <= P; ++a) xs[e * P + a] = mesh->x0 + e * hx + 0.5 * hx * (g.x[a] + 1.0);
+    xs[Nx - 1] = mesh->x1;
+    for (int e = 0; e < mesh->ny; ++e)
+        for (int a = 0; a <= P; ++a) ys[e * P + a] = mesh->y0 + e * hy + 0.5 * hy * (g.x[a] + 1.0);
+    ys[Ny - 1] = mesh->y1;
+    for (int j = 0; j < Ny; ++j)
+        for (int i = 0; i < Nx; ++i) {
+            x[(int64_t)j * Nx + i] = xs[i];
+            y[(int64_t)j * Nx + i] = ys[j];
+        }
+    return DD_OK;
+}
+
 int dd_layout(const dd_handle* h, int* layout, int* wg) {
     CHK(validate_handle(h));
     if (layout) *layout = h->layout;
@@ -1132,16 +1745,17 @@ int dd_solve_device(dd_handle* h, void* stream, const double* d_f_re, const doub
     reset_stats(h);
     const bool with_f = d_f_re != nullptr;
     if (with_f) CHK(stage_source(h, d_f_re, d_f_im));
-    HIPCHK(wdd::embed_trace(d_g_re, d_g_im, h->d_trace_idx.p, h->n_if, h->d_g0.p, h->stream));
+    HIPCHK(wdd::embed_trace(d_g_re, d_g_im, h->store->d_trace_idx.p + h->if_base, h->n_if,
+                           h->d_g0.p, h->stream));
     const int rc = solve_core(h, with_f, tol, max_iter);
     if (rc != DD_OK) {
         if (dep) (void)hipEventDestroy(dep);
         return rc;
     }
-    HIPCHK(wdd::glue_solution(h->d_u.p, h->Nx, h->Ny, h->P, h->mx, h->my, h->part.sx, h->part.sy,
+    HIPCHK(wdd::glue_solution(u_dev(h), h->Nx, h->Ny, h->P, h->mx, h->my, h->part.sx, h->part.sy,
                               h->nloc, d_u_re, d_u_im, h->stream));
     if (d_u_sub)
-        HIPCHK(hipMemcpyAsync(d_u_sub, h->d_u.p, sizeof(double2) * h->L * h->nloc,
+        HIPCHK(hipMemcpyAsync(d_u_sub, u_dev(h), sizeof(double2) * h->L * h->nloc,
                               hipMemcpyDeviceToDevice, h->stream));
     if (user) {
         HIPCHK(hipEventRecord(dep, h->stream));
@@ -1225,7 +1839,7 @@ int dd_sweep(dd_handle* h, const double* g_re, const double* g_im, const double*
     }
     if (u_re || u_im) {
         std::vector<double2> u(h->L * h->nloc);
-        HIPCHK(hipMemcpy(u.data(), h->d_u.p, sizeof(double2) * u.size(), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(u.data(), u_dev(h), sizeof(double2) * u.size(), hipMemcpyDeviceToHost));
         for (size_t i = 0; i < u.size(); ++i) {
             if (u_re) u_re[i] = u[i].x;
             if (u_im) u_im[i] = u[i].y;
@@ -1258,16 +1872,18 @@ int dd_apply_stiffness(dd_handle* h, const double* p, double* q) {
             auto a = make_args<double>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
             double* x = (double*)dp.p;
             double* y = (double*)dq.p;
-            e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_apply_node<double>(a, h->P, h->wg, x, y, h->stream)
-                : h->layout == DD_LAYOUT_PATCH ? wdd::launch_apply_patch1<double>(a, h->P, h->wg, x, y, h->stream)
-                                               : wdd::launch_apply_patch<double>(a, h->P, h->wg, x, y, h->stream);
+            e = h->layout == DD_LAYOUT_NODE     ? wdd::launch_apply_node<double>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_PATCH  ? wdd::launch_apply_patch1<double>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_STREAM ? wdd::launch_apply_stream<double>(a, h->P, h->wg, x, y, h->stream)
+                                                : wdd::launch_apply_patch<double>(a, h->P, h->wg, x, y, h->stream);
         } else {
             auto a = make_args<float>(h, h->d_g0.p, h->d_tmp.p, 0.0, false, 0.0, 1);
             float* x = (float*)dp.p;
             float* y = (float*)dq.p;
-            e = h->layout == DD_LAYOUT_NODE    ? wdd::launch_apply_node<float>(a, h->P, h->wg, x, y, h->stream)
-                : h->layout == DD_LAYOUT_PATCH ? wdd::launch_apply_patch1<float>(a, h->P, h->wg, x, y, h->stream)
-                                               : wdd::launch_apply_patch<float>(a, h->P, h->wg, x, y, h->stream);
+            e = h->layout == DD_LAYOUT_NODE     ? wdd::launch_apply_node<float>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_PATCH  ? wdd::launch_apply_patch1<float>(a, h->P, h->wg, x, y, h->stream)
+                : h->layout == DD_LAYOUT_STREAM ? wdd::launch_apply_stream<float>(a, h->P, h->wg, x, y, h->stream)
+                                                : wdd::launch_apply_patch<float>(a, h->P, h->wg, x, y, h->stream);
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -1362,6 +1978,459 @@ int dd_time_sweep(dd_handle* h, int reps, int fixed_iters, double* ms, double* d
     if (rc != DD_OK) return rc;
     *ms = h->st.sweep_seconds * 1e3 / reps;
     if (dof_updates) *dof_updates = h->st.dof_updates / reps;
+    return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct dd_batch {
+    Store* store = nullptr;
+    std::vector<dd_handle*> probs;
+    int64_t launches = 0;
+};
+
+namespace {
+
+// Layout of a placed problem in a shared store: the store's cached choice
+// for its subdomain shape, else the autotuner's (then cached).
+int choose_layout_shared(dd_handle* h) {
+    if (h->opt.layout != DD_LAYOUT_AUTO || h->layout == DD_LAYOUT_STREAM) return DD_OK;
+    Store* S = h->store;
+    const auto key = std::make_tuple(h->mx, h->my, h->P, h->opt.precision);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->layout_cache.find(key);
+        if (it != S->layout_cache.end()) {
+            layout_config(h, it->second);
+            return DD_OK;
+        }
+    }
+    CHK(autotune_layout(h));
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->layout_cache[key] = h->layout;
+    return DD_OK;
+}
+
+void batch_free(dd_batch* b) {
+    for (dd_handle* h : b->probs) {
+        if (!h) continue;
+        unplace(h);
+        delete h;
+    }
+    store_destroy(b->store);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dd_batch_destroy(dd_batch* b) {
+    if (b) batch_free(b);
+}
+
+int dd_batch_setup(dd_batch** out, int n, const dd_problem* probs, const dd_options* opt) {
+    if (!out) return fail(DD_EINVAL, "null output batch pointer");
+    *out = nullptr;
+    if (n < 1 || !probs) return fail(DD_EINVAL, "need n >= 1 problems");
+    std::vector<dd_handle*> hs(n, nullptr);
+    std::vector<HostArrays> has(n);
+    auto drop = [&]() {
+        for (dd_handle* h : hs) delete h;
+    };
+    int64_t cn = 0, ci = 0, cit = 0, ct = 0, cw = 0, cwsp = 0;
+    for (int i = 0; i < n; ++i) {
+        hs[i] = new dd_handle();
+        const dd_problem& q = probs[i];
+        const int rc = prepare(hs[i], &q.mesh, q.degree, q.wavespeed, q.omega, &q.part, opt, has[i]);
+        if (rc != DD_OK) {
+            const std::string m = g_err;
+            drop();
+            return fail(rc, "problem %d: %s", i, m.c_str());
+        }
+        problem_ranges(hs[i], 64);
+        cn += hs[i]->node_len;
+        ci += hs[i]->if_len;
+        cit += hs[i]->item_len;
+        ct += hs[i]->tab_len;
+        cw += hs[i]->w1d_len;
+        cwsp += hs[i]->wsp_len;
+    }
+    int dev = 0;
+    int rc = device_present(&dev);
+    Store* S = nullptr;
+    if (rc == DD_OK)
+        rc = store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, hs[0]->opt.precision == DD_FP32, true);
+    if (rc != DD_OK) {
+        drop();
+        return rc;
+    }
+    dd_batch* b = new dd_batch();
+    b->store = S;
+    b->probs = hs;
+    for (int i = 0; i < n && rc == DD_OK; ++i) {
+        rc = reserve(hs[i], S);
+        if (rc == DD_OK) rc = upload(hs[i], has[i]);
+        if (rc == DD_OK) rc = choose_layout_shared(hs[i]);
+        has[i] = HostArrays();
+    }
+    if (rc != DD_OK) {
+        batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return DD_OK;
+}
+
+int dd_batch_handle(dd_batch* b, int i, dd_handle** h) {
+    if (!b || !h) return fail(DD_EINVAL, "null batch or output");
+    if (i < 0 || i >= (int)b->probs.size()) return fail(DD_EINVAL, "problem index %d out of range", i);
+    *h = b->probs[i];
+    return DD_OK;
+}
+
+int dd_batch_solve(dd_batch* b, const double* const* f_re, const double* const* f_im, double tol,
+                   int max_iter, double* const* u_re, double* const* u_im, dd_stats* st, int* rcs) {
+    if (!b) return fail(DD_EINVAL, "null batch");
+    if (!u_re || !u_im) return fail(DD_EINVAL, "null output arrays");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(DD_EINVAL, "tol must be >= 0 and max_iter >= 1");
+    const int n = (int)b->probs.size();
+    for (int i = 0; i < n; ++i)
+        if (!u_re[i] || !u_im[i]) return fail(DD_EINVAL, "null output for problem %d", i);
+    Store* S = b->store;
+    const int64_t l0 = S->sched.launches;
+    std::vector<int> rc(n, DD_OK);
+    std::vector<std::string> msg(n);
+    std::vector<dd_stats> sts(n);
+    // every problem joins before any posts, so the first rendezvous waits
+    // for all of them
+    for (dd_handle* h : b->probs) {
+        h->batched = true;
+        sched_join(S);
+    }
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        th.emplace_back([&, i]() {
+            (void)hipSetDevice(S->dev);
+            rc[i] = dd_solve(b->probs[i], f_re ? f_re[i] : nullptr, f_im ? f_im[i] : nullptr,
+                             nullptr, nullptr, tol, max_iter, u_re[i], u_im[i], &sts[i]);
+            msg[i] = g_err;
+            sched_leave(S);
+        });
+    }
+    for (auto& t : th) t.join();
+    for (dd_handle* h : b->probs) h->batched = false;
+    b->launches = S->sched.launches - l0;
+    if (st) std::copy(sts.begin(), sts.end(), st);
+    if (rcs) std::copy(rc.begin(), rc.end(), rcs);
+    int worst = DD_OK;
+    for (int i = 0; i < n; ++i) {
+        if (rc[i] != DD_OK && rc[i] != DD_ENOTCONV) return fail(rc[i], "problem %d: %s", i, msg[i].c_str());
+        if (rc[i] == DD_ENOTCONV && worst == DD_OK) {
+            worst = DD_ENOTCONV;
+            fail(DD_ENOTCONV, "problem %d: %s", i, msg[i].c_str());
+        }
+    }
+    return worst;
+}
+
+int dd_batch_launches(const dd_batch* b, int64_t* launches) {
+    if (!b || !launches) return fail(DD_EINVAL, "null argument");
+    *launches = b->launches;
+    return DD_OK;
+}
+
+int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, double* dof_updates,
+                        int* launches) {
+    if (!b || !ms) return fail(DD_EINVAL, "null argument");
+    if (reps < 1 || fixed_iters < 1) return fail(DD_EINVAL, "reps and fixed_iters must be >= 1");
+    Store* S = b->store;
+    HIPCHK(hipSetDevice(S->dev));
+    std::vector<SweepReq> reqs;
+    for (dd_handle* h : b->probs) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        reqs.push_back(SweepReq{h, h->d_G.p, h->d_tmp.p, 0.0, false, h->opt.precision, 0.0,
+                                fixed_iters});
+    }
+    std::vector<SweepReq*> rp;
+    for (auto& r : reqs) rp.push_back(&r);
+    CHK(launch_batch(S, rp));
+    for (dd_handle* h : b->probs) reset_stats(h);
+    double total_ms = 0.0;
+    int groups = 0;
+    for (int r = 0; r < reps; ++r) {
+        double m = 0.0;
+        CHK(launch_batch(S, rp, &m, &groups));
+        total_ms += m;
+    }
+    *ms = total_ms / reps;
+    if (dof_updates) {
+        double d = 0.0;
+        for (dd_handle* h : b->probs) d += h->st.dof_updates;
+        *dof_updates = d / reps;
+    }
+    if (launches) *launches = groups;
+    return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving engine
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+struct Request {
+    int64_t id = 0;
+    dd_handle* h = nullptr;
+    HostArrays ha;
+    std::vector<double> fre, fim, ure, uim;
+    bool has_f = false, has_fim = false;
+    double tol = 0.0;
+    int max_iter = 0;
+    int state = DD_REQ_QUEUED;
+    int rc = DD_OK;
+    std::string msg;
+    dd_stats st{};
+    double t_submit = 0.0, t_start = 0.0, t_done = 0.0;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct dd_engine {
+    Store* store = nullptr;
+    dd_options opt;
+    size_t budget = 0, used = 0;
+    int max_active = 1;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request*> queue;
+    std::map<int64_t, Request*> reqs;
+    int running = 0;
+    int64_t peak = 0, done = 0, next_id = 1;
+    bool stop = false;
+    std::thread dispatcher;
+    std::chrono::steady_clock::time_point t0;
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+// One admitted request on its own host thread: upload, layout, batched
+// solve, release.
+void engine_run(dd_engine* e, Request* r) {
+    Store* S = e->store;
+    (void)hipSetDevice(S->dev);
+    dd_handle* h = r->h;
+    int rc = upload(h, r->ha);
+    r->ha = HostArrays();
+    if (rc == DD_OK) rc = choose_layout_shared(h);
+    if (rc == DD_OK) {
+        h->batched = true;
+        sched_join(S);
+        rc = dd_solve(h, r->has_f ? r->fre.data() : nullptr, r->has_fim ? r->fim.data() : nullptr,
+                      nullptr, nullptr, r->tol, r->max_iter, r->ure.data(), r->uim.data(), &r->st);
+        r->msg = g_err;
+        sched_leave(S);
+        h->batched = false;
+    } else {
+        r->msg = g_err;
+    }
+    unplace(h);
+    delete h;
+    r->h = nullptr;
+    r->fre = std::vector<double>();
+    r->fim = std::vector<double>();
+    std::lock_guard<std::mutex> lk(e->mu);
+    r->rc = rc;
+    r->state = DD_REQ_DONE;
+    r->t_done = e->now();
+    e->used -= r->bytes;
+    e->running -= 1;
+    e->done += 1;
+    e->cv.notify_all();
+}
+
+// Admission loop: FIFO, while a slot is free and the head request's store
+// ranges and vectors fit.
+void engine_dispatch(dd_engine* e) {
+    std::unique_lock<std::mutex> lk(e->mu);
+    while (true) {
+        while (!e->stop && !e->queue.empty() && e->running < e->max_active) {
+            Request* r = e->queue.front();
+            if (e->used + r->bytes + e->store->bytes > e->budget) break;
+            if (reserve(r->h, e->store) != DD_OK) break;
+            e->queue.pop_front();
+            e->used += r->bytes;
+            e->running += 1;
+            e->peak = std::max<int64_t>(e->peak, e->running);
+            r->state = DD_REQ_RUNNING;
+            r->t_start = e->now();
+            std::thread(engine_run, e, r).detach();
+        }
+        if (e->stop && e->running == 0) break;
+        e->cv.wait(lk);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_engine_create(dd_engine** out, size_t budget, int max_active, const dd_options* opt) {
+    if (!out) return fail(DD_EINVAL, "null output engine pointer");
+    *out = nullptr;
+    if (budget < ((size_t)64 << 20)) return fail(DD_EINVAL, "budget must be >= 64 MiB");
+    if (max_active < 1 || max_active > 4096) return fail(DD_EINVAL, "max_active must be in [1, 4096]");
+    dd_options o;
+    if (opt)
+        o = *opt;
+    else
+        dd_default_options(&o);
+    int dev = 0;
+    CHK(device_present(&dev));
+    // store: about 60% of the budget at ~200 bytes per subdomain node
+    // (coefficients, source, iterate, streaming workspace), interface and
+    // work-item spaces in proportion
+    const int64_t cn = std::max<int64_t>(1 << 16, (int64_t)(0.6 * (double)budget / 200.0));
+    const int64_t ci = cn / 2, cit = std::max<int64_t>(1024, cn / 64);
+    const int64_t ct = std::max<int64_t>(1 << 16, cn / 16), cw = 1 << 18, cwsp = cn * 5 / 2;
+    Store* S = nullptr;
+    CHK(store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, o.precision == DD_FP32, true));
+    if (S->bytes >= budget) {
+        store_destroy(S);
+        return fail(DD_ENOMEM, "budget too small for the device store");
+    }
+    dd_engine* e = new dd_engine();
+    e->store = S;
+    e->opt = o;
+    e->budget = budget;
+    e->max_active = max_active;
+    e->t0 = std::chrono::steady_clock::now();
+    e->dispatcher = std::thread(engine_dispatch, e);
+    *out = e;
+    return DD_OK;
+}
+
+void dd_engine_destroy(dd_engine* e) {
+    if (!e) return;
+    {
+        std::lock_guard<std::mutex> lk(e->mu);
+        for (Request* r : e->queue) {
+            if (r->h) delete r->h;
+            r->h = nullptr;
+            r->state = DD_REQ_DONE;
+            r->rc = DD_EINVAL;
+        }
+        e->queue.clear();
+        e->stop = true;
+        e->cv.notify_all();
+    }
+    e->dispatcher.join();
+    for (auto& kv : e->reqs) delete kv.second;
+    store_destroy(e->store);
+    delete e;
+}
+
+int dd_engine_submit(dd_engine* e, const dd_problem* prob, const double* f_re, const double* f_im,
+                     double tol, int max_iter, int64_t* id) {
+    if (!e || !prob || !id) return fail(DD_EINVAL, "null argument");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(DD_EINVAL, "tol must be >= 0 and max_iter >= 1");
+    if (!f_re && f_im) return fail(DD_EINVAL, "f_im given without f_re");
+    const double t = e->now();
+    Request* r = new Request();
+    r->h = new dd_handle();
+    int rc = prepare(r->h, &prob->mesh, prob->degree, prob->wavespeed, prob->omega, &prob->part,
+                     &e->opt, r->ha);
+    const int64_t N = rc == DD_OK ? r->h->N : 0;
+    if (rc == DD_OK) rc = check_finite(f_re, N, "f_re");
+    if (rc == DD_OK) rc = check_finite(f_im, N, "f_im");
+    if (rc == DD_OK) {
+        Store* S = e->store;
+        problem_ranges(r->h, S->align);
+        r->bytes = problem_own_bytes(r->h) + sizeof(double) * (10 * (size_t)N + 2 * (size_t)r->h->n_trace);
+        if (r->h->node_len > S->cap_node || r->h->if_len > S->cap_if ||
+            r->h->item_len > S->cap_item || r->h->tab_len > S->cap_tab ||
+            r->h->wsp_len > S->cap_wsp || r->bytes + S->bytes > e->budget)
+            rc = fail(DD_ENOMEM, "request needs more device memory than the engine holds");
+    }
+    if (rc != DD_OK) {
+        delete r->h;
+        delete r;
+        return rc;
+    }
+    r->has_f = f_re != nullptr;
+    r->has_fim = f_im != nullptr;
+    if (f_re) r->fre.assign(f_re, f_re + N);
+    if (f_im) r->fim.assign(f_im, f_im + N);
+    r->ure.assign(N, 0.0);
+    r->uim.assign(N, 0.0);
+    r->tol = tol;
+    r->max_iter = max_iter;
+    r->t_submit = t;
+    std::lock_guard<std::mutex> lk(e->mu);
+    r->id = e->next_id++;
+    e->reqs[r->id] = r;
+    e->queue.push_back(r);
+    e->cv.notify_all();
+    *id = r->id;
+    return DD_OK;
+}
+
+int dd_engine_status(dd_engine* e, int64_t id, int* state) {
+    if (!e || !state) return fail(DD_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto it = e->reqs.find(id);
+    if (it == e->reqs.end()) return fail(DD_EINVAL, "unknown request %lld", (long long)id);
+    *state = it->second->state;
+    return DD_OK;
+}
+
+int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stats* st,
+                   double* times) {
+    if (!e) return fail(DD_EINVAL, "null engine");
+    Request* r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(e->mu);
+        auto it = e->reqs.find(id);
+        if (it == e->reqs.end()) return fail(DD_EINVAL, "unknown request %lld", (long long)id);
+        r = it->second;
+        e->cv.wait(lk, [&] { return r->state == DD_REQ_DONE; });
+        e->reqs.erase(it);
+    }
+    if (u_re) std::copy(r->ure.begin(), r->ure.end(), u_re);
+    if (u_im) std::copy(r->uim.begin(), r->uim.end(), u_im);
+    if (st) *st = r->st;
+    if (times) {
+        times[0] = r->t_submit;
+        times[1] = r->t_start;
+        times[2] = r->t_done;
+    }
+    const int rc = r->rc;
+    const std::string msg = r->msg;
+    delete r;
+    if (rc != DD_OK) g_err = msg;
+    return rc;
+}
+
+int dd_engine_get_info(dd_engine* e, dd_engine_info* info) {
+    if (!e || !info) return fail(DD_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(e->mu);
+    info->queued = (int64_t)e->queue.size();
+    info->running = e->running;
+    info->done = e->done;
+    info->peak_running = e->peak;
+    info->budget_bytes = e->budget;
+    info->store_bytes = e->store->bytes;
+    info->request_bytes = e->used;
+    info->launches = e->store->sched.launches.load();
     return DD_OK;
 }
 

@@ -18,7 +18,7 @@ struct SubDesc {
     int nxl, nyl;        // local node grid
     int nt;              // leapfrog steps per period
     int toff;            // offset of this subdomain's filter tables
-    int pad0;
+    int max_wh;          // > 0: this item's WaveHoltz cap and tolerance (tau) override the launch's
     int64_t node_off;    // first local node in the per-node arrays
     int64_t w_off;       // first entry of its 1D weights: nxl along x, then nyl along y
     int64_t if_off;      // first slot of this subdomain's 4 sides (g layout)
@@ -27,6 +27,8 @@ struct SubDesc {
     double pd0c, pd0s;   // omega cos(pi/N_t), omega sin(pi/N_t): pdot^{1/2} from u
     double two_over_nt;  // 2 / N_t
     double sx_ref, sy_ref;  // 2/hx, 2/hy: reference-to-physical stiffness scales
+    int64_t ws_off;      // STREAM layout: first element of its two zero-padded p grids
+    double tau;          // see max_wh
 };
 
 // Per-node coefficient arrays of a sweep in the sweep precision `Real`.
@@ -58,6 +60,9 @@ struct SweepArgs {
     int* wh_iters;           // per item: WaveHoltz iterations performed
     double tau;              // inner tolerance (<= 0: fixed count)
     int max_wh;              // iteration cap / fixed count
+    Real* ws_p;              // STREAM layout: padded p grids (2 per subdomain, at desc.ws_off)
+    Real* ws_s;              // STREAM layout: pd, vr, vi, beta*Re b, beta*Im b (node-indexed)
+    int64_t ws_stride;       // distance between those five arrays
     size_t lds_bytes;        // dynamic LDS per workgroup of the launch
     int nt_max;              // largest N_t of the launch (sizes the LDS tables)
     double K1[kMaxP + 1][kMaxP + 1][kMaxP + 1];  // K1[P][a][b]: reference D^T W D
@@ -79,7 +84,17 @@ hipError_t launch_apply_patch(const SweepArgs<Real>& a, int P, int wg, const Rea
 template <typename Real>
 hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
                              hipStream_t s);
+template <typename Real>
+hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
+template <typename Real>
+hipError_t launch_apply_stream(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
+                               hipStream_t s);
 size_t patch_lds_bytes(int mx, int my, int P, int nt_max, size_t real_size);
+size_t stream_lds_bytes(int P, int nt_max, size_t real_size);
+// Zero-padded p grid of a STREAM subdomain: kMaxP extra nodes on every side.
+__host__ __device__ inline int64_t stream_pad_nodes(int nxl, int nyl) {
+    return (int64_t)(nxl + 2 * kMaxP) * (nyl + 2 * kMaxP);
+}
 size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size);
 size_t patch1_lds_bytes(int mx, int my, int P, int wg, int nt_max, size_t real_size);
 

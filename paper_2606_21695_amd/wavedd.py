@@ -18,15 +18,20 @@ LIB_PATH = os.path.join(HERE, "libwavedd.so")
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ENAN, DD_ENOTCONV, DD_ENODEV = 0, -1, -2, -3, -4, -5, -6
 DD_FP64, DD_FP32 = 0, 1
-DD_LAYOUT_AUTO, DD_LAYOUT_NODE, DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG = 0, 1, 2, 3
+DD_LAYOUT_AUTO, DD_LAYOUT_NODE, DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_STREAM = 0, 1, 2, 3, 4
 DD_OUTER_GMRES, DD_OUTER_FIXED = 0, 1
 
 EXPORTS = [
     "dd_default_options", "dd_setup", "dd_destroy", "dd_last_error", "dd_sizes",
     "dd_node_coords", "dd_time_steps", "dd_solve", "dd_solve_device", "dd_sweep",
     "dd_apply_stiffness", "dd_residual", "dd_apply_operator_device", "dd_get_state",
-    "dd_set_state", "dd_time_sweep", "dd_layout",
+    "dd_set_state", "dd_time_sweep", "dd_layout", "dd_mesh_coords",
+    "dd_batch_setup", "dd_batch_destroy", "dd_batch_handle", "dd_batch_solve",
+    "dd_batch_time_sweep", "dd_batch_launches",
+    "dd_engine_create", "dd_engine_destroy", "dd_engine_submit", "dd_engine_status",
+    "dd_engine_wait", "dd_engine_get_info",
 ]
+DD_REQ_QUEUED, DD_REQ_RUNNING, DD_REQ_DONE = 0, 1, 2
 
 
 class dd_mesh(C.Structure):
@@ -51,6 +56,21 @@ class dd_stats(C.Structure):
                 ("wh_iters_max", C.c_int), ("nt_min", C.c_int), ("nt_max", C.c_int),
                 ("dof_updates", C.c_double), ("sweep_seconds", C.c_double),
                 ("seconds", C.c_double), ("refine_steps", C.c_int), ("fp64_sweeps", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class dd_problem(C.Structure):
+    _fields_ = [("mesh", dd_mesh), ("degree", C.c_int), ("wavespeed", C.POINTER(C.c_double)),
+                ("omega", C.c_double), ("part", dd_partition)]
+
+
+class dd_engine_info(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("done", C.c_int64),
+                ("launches", C.c_int64), ("peak_running", C.c_int64),
+                ("budget_bytes", C.c_size_t), ("store_bytes", C.c_size_t),
+                ("request_bytes", C.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -117,6 +137,23 @@ def load():
         "dd_set_state": ([P, D], C.c_int),
         "dd_time_sweep": ([P, C.c_int, C.c_int, D, D], C.c_int),
         "dd_layout": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "dd_mesh_coords": ([C.POINTER(dd_mesh), C.c_int, D, D], C.c_int),
+        "dd_batch_setup": ([C.POINTER(P), C.c_int, C.POINTER(dd_problem),
+                            C.POINTER(dd_options)], C.c_int),
+        "dd_batch_destroy": ([P], None),
+        "dd_batch_handle": ([P, C.c_int, C.POINTER(P)], C.c_int),
+        "dd_batch_solve": ([P, C.POINTER(D), C.POINTER(D), C.c_double, C.c_int, C.POINTER(D),
+                            C.POINTER(D), C.POINTER(dd_stats), C.POINTER(C.c_int)], C.c_int),
+        "dd_batch_time_sweep": ([P, C.c_int, C.c_int, D, D, C.POINTER(C.c_int)], C.c_int),
+        "dd_batch_launches": ([P, I64], C.c_int),
+        "dd_engine_create": ([C.POINTER(P), C.c_size_t, C.c_int, C.POINTER(dd_options)],
+                             C.c_int),
+        "dd_engine_destroy": ([P], None),
+        "dd_engine_submit": ([P, C.POINTER(dd_problem), D, D, C.c_double, C.c_int, I64],
+                             C.c_int),
+        "dd_engine_status": ([P, C.c_int64, C.POINTER(C.c_int)], C.c_int),
+        "dd_engine_wait": ([P, C.c_int64, D, D, C.POINTER(dd_stats), D], C.c_int),
+        "dd_engine_get_info": ([P, C.POINTER(dd_engine_info)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -309,6 +346,129 @@ def dd_time_sweep(h, reps=10, fixed_iters=0):
     ms, du = C.c_double(), C.c_double()
     _check(load().dd_time_sweep(h, reps, fixed_iters, C.byref(ms), C.byref(du)))
     return ms.value, du.value
+
+
+def dd_mesh_coords(nx, ny, degree, x0=0.0, x1=1.0, y0=0.0, y1=1.0):
+    """Global GLL node coordinates of a mesh (host computation, no handle)."""
+    mesh = dd_mesh(nx, ny, x0, x1, y0, y1)
+    n = (nx * degree + 1) * (ny * degree + 1)
+    x, y = np.empty(n), np.empty(n)
+    _check(load().dd_mesh_coords(C.byref(mesh), degree, _dp(x), _dp(y)))
+    return x, y
+
+
+def _problem(spec):
+    """(dd_problem, keep-alive wavespeed array) from a dict with keys nx, ny,
+    P, x0, x1, y0, y1, sx, sy, omega, c (nodal wavespeed array)."""
+    c = _f64(spec["c"])
+    q = dd_problem(dd_mesh(spec["nx"], spec["ny"], spec["x0"], spec["x1"], spec["y0"], spec["y1"]),
+                   spec["P"], _dp(c), spec["omega"], dd_partition(spec["sx"], spec["sy"]))
+    return q, c
+
+
+def workload_spec(wl):
+    """Problem dict of a workload with its wavespeed and source sampled at
+    the mesh's GLL nodes."""
+    X, Y = dd_mesh_coords(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+    return dict(nx=wl.nx, ny=wl.ny, P=wl.P, x0=wl.x0, x1=wl.x1, y0=wl.y0, y1=wl.y1, sx=wl.sx,
+                sy=wl.sy, omega=wl.omega, c=np.asarray(wl.c(X, Y), dtype=float),
+                f=np.asarray(wl.f(X, Y), dtype=float), tol=wl.tol, X=X, Y=Y)
+
+
+def dd_batch_setup(specs, options=None):
+    """Batch of problem dicts (see _problem).  Returns an opaque pointer."""
+    qs = [_problem(s) for s in specs]
+    arr = (dd_problem * len(qs))(*[q for q, _ in qs])
+    b = C.c_void_p()
+    _check(load().dd_batch_setup(C.byref(b), len(qs), arr,
+                                 C.byref(options) if options is not None else None))
+    return b
+
+
+def dd_batch_destroy(b):
+    load().dd_batch_destroy(b)
+
+
+def dd_batch_handle(b, i):
+    h = C.c_void_p()
+    _check(load().dd_batch_handle(b, i, C.byref(h)))
+    return h
+
+
+def dd_batch_solve(b, fs, tol=1e-8, max_iter=1000, allow_notconv=False):
+    """Solve every problem of the batch; fs: list of real nodal sources (or
+    None).  Returns (list of complex u, list of stats dicts, per-problem
+    codes, overall code)."""
+    n = len(fs)
+    sizes = [dd_sizes(dd_batch_handle(b, i))["n_global"] for i in range(n)]
+    keep = [None if f is None else _f64(f) for f in fs]
+    PD = C.POINTER(C.c_double)
+    f_re = (PD * n)(*[_dp(f) if f is not None else PD() for f in keep])
+    ure = [np.empty(m) for m in sizes]
+    uim = [np.empty(m) for m in sizes]
+    u_re = (PD * n)(*[_dp(u) for u in ure])
+    u_im = (PD * n)(*[_dp(u) for u in uim])
+    st = (dd_stats * n)()
+    rcs = (C.c_int * n)()
+    rc = load().dd_batch_solve(b, f_re, None, tol, max_iter, u_re, u_im, st, rcs)
+    _check(rc, (DD_ENOTCONV,) if allow_notconv else ())
+    return ([ure[i] + 1j * uim[i] for i in range(n)], [st[i].as_dict() for i in range(n)],
+            list(rcs), rc)
+
+
+def dd_batch_time_sweep(b, reps=5, fixed_iters=5):
+    ms, du, nl = C.c_double(), C.c_double(), C.c_int()
+    _check(load().dd_batch_time_sweep(b, reps, fixed_iters, C.byref(ms), C.byref(du),
+                                      C.byref(nl)))
+    return ms.value, du.value, nl.value
+
+
+def dd_batch_launches(b):
+    v = C.c_int64()
+    _check(load().dd_batch_launches(b, C.byref(v)))
+    return v.value
+
+
+def dd_engine_create(budget_bytes, max_active, options=None):
+    e = C.c_void_p()
+    _check(load().dd_engine_create(C.byref(e), int(budget_bytes), max_active,
+                                   C.byref(options) if options is not None else None))
+    return e
+
+
+def dd_engine_destroy(e):
+    load().dd_engine_destroy(e)
+
+
+def dd_engine_submit(e, spec, f=None, tol=1e-6, max_iter=1000):
+    q, keep = _problem(spec)
+    fr = _f64(f)
+    rid = C.c_int64()
+    _check(load().dd_engine_submit(e, C.byref(q), _dp(fr), None, tol, max_iter, C.byref(rid)))
+    return rid.value
+
+
+def dd_engine_status(e, rid):
+    s = C.c_int()
+    _check(load().dd_engine_status(e, rid, C.byref(s)))
+    return s.value
+
+
+def dd_engine_wait(e, rid, n_global, allow_notconv=False):
+    """Block for request rid; returns (u complex, stats dict, (t_submit,
+    t_start, t_done), code)."""
+    ure, uim = np.empty(n_global), np.empty(n_global)
+    st = dd_stats()
+    t = np.empty(3)
+    rc = load().dd_engine_wait(e, rid, _dp(ure), _dp(uim), C.byref(st), _dp(t))
+    _check(rc, (DD_ENOTCONV,) if allow_notconv else ())
+    return ure + 1j * uim, st.as_dict(), tuple(t), rc
+
+
+def dd_engine_get_info(e):
+    info = dd_engine_info()
+    _check(load().dd_engine_get_info(e, C.byref(info)))
+    return info.as_dict()
 
 
 class Problem:

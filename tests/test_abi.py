@@ -88,3 +88,62 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.dd_sizes(None, None, None, None, None, None) == wavedd.DD_EINVAL
     assert lib.dd_layout(None, None, None) == wavedd.DD_EINVAL
     lib.dd_destroy(None)
+
+
+def test_mesh_coords_match_oracle():
+    """Host-side node coordinates (no handle, no device) equal the oracle's
+    GLL node coordinates."""
+    from oracle import sem
+    for (nx, ny, P, box) in [(3, 2, 1, (0, 1, 0, 1)), (4, 5, 3, (-1.0, 2.0, 0.5, 1.25)),
+                             (2, 2, 4, (0, 1, 0, 2))]:
+        x, y = wavedd.dd_mesh_coords(nx, ny, P, *box)
+        X, Y = sem.node_coords(sem.Rect(nx, ny, P, *box))
+        assert np.abs(x - X).max() < 1e-14 and np.abs(y - Y).max() < 1e-14
+
+
+def test_mesh_coords_rejects_bad_arguments():
+    lib = wavedd.load()
+    x = np.empty(100)
+    m = wavedd.dd_mesh(2, 2, 0.0, 1.0, 0.0, 1.0)
+    assert lib.dd_mesh_coords(C.byref(m), 0, wavedd._dp(x), wavedd._dp(x)) == wavedd.DD_EINVAL
+    m = wavedd.dd_mesh(2, 2, 1.0, 1.0, 0.0, 1.0)
+    assert lib.dd_mesh_coords(C.byref(m), 2, wavedd._dp(x), wavedd._dp(x)) == wavedd.DD_EINVAL
+
+
+def _spec(nx=4, ny=4, P=2, sx=2, sy=2, omega=3.0):
+    N = (nx * P + 1) * (ny * P + 1)
+    return dict(nx=nx, ny=ny, P=P, x0=0.0, x1=1.0, y0=0.0, y1=1.0, sx=sx, sy=sy, omega=omega,
+                c=np.ones(N))
+
+
+def test_batch_setup_names_the_bad_problem():
+    specs = [_spec(), _spec(sx=3), _spec()]
+    with pytest.raises(wavedd.WaveddError) as ei:
+        wavedd.dd_batch_setup(specs)
+    assert ei.value.code == wavedd.DD_EINVAL and "problem 1" in str(ei.value)
+    lib = wavedd.load()
+    assert lib.dd_batch_setup(None, 1, None, None) == wavedd.DD_EINVAL
+    b = C.c_void_p()
+    assert lib.dd_batch_setup(C.byref(b), 0, None, None) == wavedd.DD_EINVAL
+    lib.dd_batch_destroy(None)
+
+
+def test_engine_rejects_bad_arguments():
+    lib = wavedd.load()
+    e = C.c_void_p()
+    assert lib.dd_engine_create(C.byref(e), 1 << 20, 4, None) == wavedd.DD_EINVAL
+    assert lib.dd_engine_create(C.byref(e), 1 << 30, 0, None) == wavedd.DD_EINVAL
+    assert lib.dd_engine_create(None, 1 << 30, 4, None) == wavedd.DD_EINVAL
+    lib.dd_engine_destroy(None)
+
+
+def test_no_device_is_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(wavedd.WaveddError) as ei:
+        wavedd.dd_batch_setup([_spec(), _spec(P=3)])
+    assert ei.value.code == wavedd.DD_ENODEV
+    with pytest.raises(wavedd.WaveddError) as ei:
+        wavedd.dd_engine_create(1 << 30, 4)
+    assert ei.value.code == wavedd.DD_ENODEV

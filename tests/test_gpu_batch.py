@@ -1,0 +1,181 @@
+"""GPU: batched launches (the subdomains of several problems in one launch)
+and the serving engine, through the C ABI, against single-problem solves of
+the same problems and against the oracle.
+
+A batched launch runs each subdomain's work item exactly as a launch of its
+own problem does (same kernel, same data, same per-item WaveHoltz
+tolerance), and every problem keeps its own outer iteration, so with the
+same layout the batched solution equals the single-problem solution bit
+for bit; the oracle bar is the single-solve bar (FP64 1e-10 at equal outer
+tolerance)."""
+import numpy as np
+import pytest
+
+from oracle import dd, sem
+
+pytestmark = pytest.mark.gpu
+
+# nx, ny, P, sx, sy, omega, box: mixed degrees, shapes and layouts; the last
+# has 24x24-element subdomains (5329 nodes), which only STREAM holds
+SPECS = [
+    (8, 8, 2, 2, 2, 10.0, (0.0, 1.0, 0.0, 1.0)),
+    (6, 4, 3, 2, 2, 9.0, (0.0, 1.5, 0.0, 1.0)),
+    (4, 6, 1, 2, 3, 6.0, (0.0, 1.0, 0.0, 1.0)),
+    (4, 4, 4, 2, 1, 8.0, (0.2, 1.2, 0.0, 1.0)),
+    (48, 24, 3, 2, 1, 20.0, (0.0, 2.0, 0.0, 1.0)),
+]
+
+
+def _c(X, Y):
+    return 1.0 + 0.3 * np.sin(4 * X + 0.5) * np.cos(3 * Y - 0.1)
+
+
+def _f(X, Y, k):
+    x0, y0 = X.min() + 0.37 * (X.max() - X.min()), Y.min() + (0.3 + 0.1 * k) * (Y.max() - Y.min())
+    return np.exp(-((X - x0) ** 2 + (Y - y0) ** 2) / (2 * 0.06 ** 2))
+
+
+def _spec(W, k):
+    nx, ny, P, sx, sy, om, box = SPECS[k]
+    X, Y = W.dd_mesh_coords(nx, ny, P, *box)
+    return dict(nx=nx, ny=ny, P=P, x0=box[0], x1=box[1], y0=box[2], y1=box[3], sx=sx, sy=sy,
+                omega=om, c=_c(X, Y), f=_f(X, Y, k), X=X, Y=Y)
+
+
+def _single(W, s, tol, **opt):
+    o = W.dd_default_options(**opt)
+    h = W.dd_setup(s["nx"], s["ny"], s["P"], s["c"], s["omega"], s["sx"], s["sy"], s["x0"],
+                   s["x1"], s["y0"], s["y1"], o)
+    u, st, _ = W.dd_solve(h, s["f"], None, tol)
+    W.dd_destroy(h)
+    return u, st
+
+
+def test_batch_matches_single_solves(gpu_lib):
+    W = gpu_lib
+    specs = [_spec(W, k) for k in range(len(SPECS))]
+    o = W.dd_default_options(tau_in=1e-12)
+    b = W.dd_batch_setup(specs, o)
+    try:
+        lays = [W.dd_layout(W.dd_batch_handle(b, i))[0] for i in range(len(specs))]
+        print(f"batch layouts {lays}", flush=True)
+        assert lays[-1] == W.DD_LAYOUT_STREAM
+        us, sts, rcs, rc = W.dd_batch_solve(b, [s["f"] for s in specs], 1e-8)
+        launches = W.dd_batch_launches(b)
+    finally:
+        W.dd_batch_destroy(b)
+    assert rc == W.DD_OK and all(r == W.DD_OK for r in rcs)
+    # one launch round per sweep of the problem with the most sweeps
+    assert launches == max(st["sweeps"] for st in sts)
+    for i, s in enumerate(specs):
+        u1, st1 = _single(W, s, 1e-8, tau_in=1e-12, layout=lays[i])
+        print(f"problem {i}: batch iters {sts[i]['outer_iters']} single {st1['outer_iters']}",
+              flush=True)
+        assert sts[i]["outer_iters"] == st1["outer_iters"]
+        assert np.array_equal(us[i], u1), i
+
+
+@pytest.mark.parametrize("k", [0, 3, 4])
+def test_batch_matches_oracle(gpu_lib, k):
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(len(SPECS))]
+    b = W.dd_batch_setup(specs, W.dd_default_options(tau_in=1e-12))
+    try:
+        us, sts, rcs, rc = W.dd_batch_solve(b, [s["f"] for s in specs], 1e-8)
+    finally:
+        W.dd_batch_destroy(b)
+    s = specs[k]
+    mesh = sem.Rect(s["nx"], s["ny"], s["P"], s["x0"], s["x1"], s["y0"], s["y1"])
+    X, Y = sem.node_coords(mesh)
+    dec = dd.Decomposition(mesh, dd.Partition(s["sx"], s["sy"]), _c(X, Y), s["omega"])
+    us_ref, info = dd.solve_dd(dec, _f(X, Y, k), tol=1e-8)
+    assert sts[k]["outer_iters"] == info["iters"]
+    u_ref = dec.glue(us_ref)
+    assert np.linalg.norm(us[k] - u_ref) / np.linalg.norm(u_ref) < 1e-10
+
+
+def test_batch_fp32_relaxed_reaches_tolerance(gpu_lib):
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(len(SPECS))]
+    b = W.dd_batch_setup(specs, W.dd_default_options(precision=W.DD_FP32, tau_in=1e-6, relax=0.1))
+    try:
+        us, sts, rcs, rc = W.dd_batch_solve(b, [s["f"] for s in specs], 1e-8)
+        res = [W.dd_residual(W.dd_batch_handle(b, i), us[i], specs[i]["f"])
+               for i in range(len(specs))]
+    finally:
+        W.dd_batch_destroy(b)
+    assert rc == W.DD_OK
+    for i, s in enumerate(specs):
+        u64, _ = _single(W, s, 1e-8, tau_in=1e-12)
+        assert np.linalg.norm(us[i] - u64) / np.linalg.norm(u64) < 1e-6, i
+        assert sts[i]["true_rel_residual"] <= 1e-8
+        assert res[i] < 1e-6
+
+
+def test_batch_time_sweep_counts_dof_updates(gpu_lib):
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(len(SPECS))]
+    b = W.dd_batch_setup(specs)
+    try:
+        expect = 0.0
+        for i in range(len(specs)):
+            h = W.dd_batch_handle(b, i)
+            nt = W.dd_time_steps(h)
+            expect += W.dd_sizes(h)["n_local"] * float((nt - 1).sum()) * 3
+        ms, dof, launches = W.dd_batch_time_sweep(b, reps=2, fixed_iters=3)
+    finally:
+        W.dd_batch_destroy(b)
+    assert ms > 0 and launches >= 1
+    assert dof == expect
+
+
+def _engine_run(W, specs, order, budget=4 << 30, max_active=3, **opt):
+    e = W.dd_engine_create(budget, max_active, W.dd_default_options(**opt))
+    try:
+        ids = [W.dd_engine_submit(e, specs[k], specs[k]["f"], 1e-8) for k in order]
+        out = [W.dd_engine_wait(e, rid, specs[k]["c"].size) for rid, k in zip(ids, order)]
+        info = W.dd_engine_get_info(e)
+    finally:
+        W.dd_engine_destroy(e)
+    return out, info
+
+
+def test_engine_mix_matches_alone_and_single(gpu_lib):
+    """Each request's answer is the same in a mix of concurrent requests, in
+    the engine alone, and from a plain dd_solve (layout fixed to STREAM so
+    all three launch identical work items)."""
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(len(SPECS))]
+    order = [4, 0, 1, 2, 3, 1, 0]
+    mix, info = _engine_run(W, specs, order, tau_in=1e-12, layout=W.DD_LAYOUT_STREAM)
+    print(f"engine info {info}", flush=True)
+    assert info["done"] == len(order) and info["peak_running"] <= 3
+    assert all(rc == W.DD_OK for *_, rc in mix)
+    alone, _ = _engine_run(W, specs, [1], tau_in=1e-12, layout=W.DD_LAYOUT_STREAM)
+    assert np.array_equal(alone[0][0], mix[2][0]) and np.array_equal(mix[2][0], mix[5][0])
+    for (u, st, times, rc), k in zip(mix, order):
+        u1, st1 = _single(W, specs[k], 1e-8, tau_in=1e-12, layout=W.DD_LAYOUT_STREAM)
+        assert st["outer_iters"] == st1["outer_iters"], k
+        assert np.array_equal(u, u1), k
+        assert times[0] <= times[1] <= times[2]
+
+
+def test_engine_admission_under_a_small_budget(gpu_lib):
+    """A 64 MiB engine admits requests as memory frees up and rejects one
+    larger than all it holds."""
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(4)]
+    out, info = _engine_run(W, specs, [0, 1, 2, 3, 0, 1], budget=64 << 20, max_active=8,
+                            tau_in=1e-12)
+    assert info["done"] == 6 and all(rc == W.DD_OK for *_, rc in out)
+    e = W.dd_engine_create(64 << 20, 2)
+    try:
+        nx = ny = 400
+        X, Y = W.dd_mesh_coords(nx, ny, 2)
+        big = dict(nx=nx, ny=ny, P=2, x0=0.0, x1=1.0, y0=0.0, y1=1.0, sx=8, sy=8, omega=10.0,
+                   c=np.ones(X.size))
+        with pytest.raises(W.WaveddError) as ei:
+            W.dd_engine_submit(e, big, None, 1e-6)
+        assert ei.value.code == W.DD_ENOMEM
+    finally:
+        W.dd_engine_destroy(e)

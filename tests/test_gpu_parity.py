@@ -48,7 +48,7 @@ def _rel(a, b):
 
 
 SHAPES = [(6, 4, 3, 2, 2), (8, 8, 2, 2, 2), (4, 6, 1, 2, 3), (4, 4, 4, 2, 1), (3, 5, 3, 1, 1)]
-LAYOUTS = [1, 2, 3]  # DD_LAYOUT_NODE, DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG
+LAYOUTS = [1, 2, 3, 4]  # DD_LAYOUT_NODE, _PATCH, _PATCH_XCHG, _STREAM
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -147,7 +147,96 @@ def test_autotuned_layout_is_a_fitting_layout(gpu_lib):
     h, _, _ = _setup(W, 8, 8, 2, 2, 2, 10.0, _cwave)  # auto
     lay, wg = W.dd_layout(h)
     W.dd_destroy(h)
-    assert lay in (1, 2, 3) and wg % 64 == 0
+    assert lay in (1, 2, 3) and wg % 64 == 0   # on-chip layouts when they fit
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stream_matches_node_bitwise(gpu_lib, prec):
+    """STREAM performs the NODE layout's per-node arithmetic in the same
+    order (and, with one node per thread, the same stop-test sums): the
+    sweeps agree bit for bit."""
+    W = gpu_lib
+    nx, ny, P, sx, sy = 6, 4, 3, 2, 2
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, 9.0, _cwave)
+    g = _random_g(dec, 3)
+    out = []
+    for lay in (1, 4):
+        h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, 9.0, _cwave, precision=prec, layout=lay,
+                           tau_in=1e-9 if prec == 0 else 1e-5)
+        fl = np.exp(-((Xl - 0.4) ** 2 + (Yl - 0.55) ** 2) / 0.02)
+        out.append(W.dd_sweep(h, g, fl, 1.0))
+        W.dd_destroy(h)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_stream_solve_large_subdomains_matches_oracle_dd(gpu_lib):
+    """2x2 subdomains of 24x24 elements at P=3 (5329 nodes each, more than
+    the on-chip layouts hold): auto picks STREAM; the FP64 solve follows
+    the oracle DD's GMRES path."""
+    W = gpu_lib
+    nx = ny = 48
+    P, sx, sy, om = 3, 2, 2, 25.0
+    h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, tau_in=1e-12)
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, om, _cwave)
+    lay, wg = W.dd_layout(h)
+    assert lay == 4 and wg == 1024
+
+    def src(X, Y):
+        return np.exp(-((X - 0.37) ** 2 + (Y - 0.58) ** 2) / (2 * 0.04 ** 2))
+    u, st, _ = W.dd_solve(h, src(Xl, Yl), None, 1e-8)
+    W.dd_destroy(h)
+    us_ref, info = dd.solve_dd(dec, src(X, Y), tol=1e-8)
+    print(f"stream solve gpu iters={st['outer_iters']} oracle={info['iters']}", flush=True)
+    assert st["outer_iters"] == info["iters"]
+    assert _rel([u], [dec.glue(us_ref)]) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c3_full_size_sweep_sampled(gpu_lib, prec):
+    """The 512x512-element P=3 waveguide with 8x8 subdomains (193x193 nodes
+    each, STREAM) at full size: one sweep of two fixed WaveHoltz iterations
+    from random interface data, in the launch configuration of a solve.
+    Sampled subdomains (corner, edge, interior) are recomputed one by one by
+    the oracle's WaveHoltz on that subdomain alone."""
+    import workloads
+    W = gpu_lib
+    wl = workloads.c3()
+    m = 2
+    h, Xl, Yl = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, precision=prec,
+                       tau_in=0.0, max_wh=m)
+    lay, _ = W.dd_layout(h)
+    assert lay == 4
+    sizes = W.dd_sizes(h)
+    L, nloc, n_if = sizes["n_sub"], sizes["n_local"], sizes["n_iface"]
+    rng = np.random.default_rng(33)
+    g = rng.standard_normal(n_if) + 1j * rng.standard_normal(n_if)
+    print(f"c3 sweep prec={prec} L={L} nloc={nloc}", flush=True)
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, wl.f(Xl, Yl), 1.0)
+    W.dd_destroy(h)
+    assert (its == m).all()
+    mesh = sem.Rect(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+    mx, my = wl.nx // wl.sx, wl.ny // wl.sy
+    nxl, nyl = mx * wl.P + 1, my * wl.P + 1
+    per = 2 * nxl + 2 * nyl
+    X, Y = sem.node_coords(mesh)
+    c, f = wl.c(X, Y), wl.f(X, Y)
+    tol = 1e-11 if prec == 0 else 1e-4
+    for l in (0, 13, 63):
+        a, b = l % wl.sx, l // wl.sx
+        x0, y0 = wl.x0 + a * mx * mesh.hx, wl.y0 + b * my * mesh.hy
+        sub = sem.Rect(mx, my, wl.P, x0, x0 + mx * mesh.hx, y0, y0 + my * mesh.hy)
+        i = a * mx * wl.P + np.arange(nxl)
+        j = b * my * wl.P + np.arange(nyl)
+        gl = (j[:, None] * mesh.Nx + i[None, :]).ravel()
+        one = dd.Decomposition(sub, dd.Partition(1, 1), c[gl], wl.omega)
+        fl = np.zeros(sub.N)
+        fl[:] = f[gl]
+        b_l = one.rhs(0, fl, g[l * per:(l + 1) * per], 1.0)
+        sd = one.subs[0]
+        nt = wh.subdomain_steps(one)[0]
+        u_ref, it = wh.solve(sd["A"], sd["M"], sd["H"], b_l, wl.omega, nt, fixed_iters=m)
+        assert _rel([u_gpu[l * nloc:(l + 1) * nloc]], [u_ref]) < tol, l
 
 
 def test_sweep_is_deterministic(gpu_lib):
