@@ -291,7 +291,9 @@ struct Store {
     DBuf<int> d_gidx, d_iters, d_is_iface;
     DBuf<int64_t> d_trace_idx;
     DBuf<double2> d_u;
-    DBuf<double> d_wsp, d_wss;       // STREAM layout workspace
+    DBuf<double> d_wsp, d_wss;       // STREAM layout workspace, FP64 sweeps
+    DBuf<float> d_wsp32, d_wss32;    // STREAM layout workspace, FP32 sweeps (own bytes: FP64 and
+                                     // FP32 sweeps of different problems run concurrently)
     DBuf<double2> d_gin, d_gout;     // shared: per-problem sweep input / output ranges
     DBuf<wdd::SubDesc> d_work;       // shared: work lists of batched launches
     DBuf<int> d_work_iters;
@@ -389,8 +391,13 @@ wdd::SweepArgs<Real> store_args(const Store* S, const double2* g_in, double2* g_
     a.u = S->d_u.p;
     a.tau = tau;
     a.max_wh = max_wh;
-    a.ws_p = reinterpret_cast<Real*>(S->d_wsp.p);
-    a.ws_s = reinterpret_cast<Real*>(S->d_wss.p);
+    if (sizeof(Real) == 4) {
+        a.ws_p = reinterpret_cast<Real*>(S->d_wsp32.p);
+        a.ws_s = reinterpret_cast<Real*>(S->d_wss32.p);
+    } else {
+        a.ws_p = reinterpret_cast<Real*>(S->d_wsp.p);
+        a.ws_s = reinterpret_cast<Real*>(S->d_wss.p);
+    }
     a.ws_stride = n;
     std::memcpy(a.K1, K1, sizeof(a.K1));
     return a;
@@ -1336,7 +1343,7 @@ void store_destroy(Store* S) {
     S->d_desc.free();
     S->d_w1d.free(); S->d_kside.free(); S->d_area.free();
     S->d_gidx.free(); S->d_iters.free(); S->d_is_iface.free(); S->d_trace_idx.free();
-    S->d_u.free(); S->d_wsp.free(); S->d_wss.free();
+    S->d_u.free(); S->d_wsp.free(); S->d_wss.free(); S->d_wsp32.free(); S->d_wss32.free();
     S->d_gin.free(); S->d_gout.free(); S->d_work.free(); S->d_work_iters.free();
     if (S->h_work) (void)hipHostFree(S->h_work);
     if (S->h_work_iters) (void)hipHostFree(S->h_work_iters);
@@ -1408,6 +1415,11 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
         STCHK(S->d_wsp.alloc(cwsp));
         STCHK(S->d_wss.alloc(5 * cn));
         bytes += 8 * (cwsp + 5 * cn);
+        if (fp32) {
+            STCHK(S->d_wsp32.alloc(cwsp));
+            STCHK(S->d_wss32.alloc(5 * cn));
+            bytes += 4 * (cwsp + 5 * cn);
+        }
     }
     STCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
     STCHK(hipEventCreate(&S->ev0));
@@ -1553,6 +1565,8 @@ int upload(dd_handle* h, const HostArrays& ha) {
     if (h->wsp_len > 0) {
         // the zero padding of the p grids is never written: clear once
         HIPCHK(hipMemset(S->d_wsp.p + h->wsp_base, 0, sizeof(double) * h->wsp_len));
+        if (S->d_wsp32.p)
+            HIPCHK(hipMemset(S->d_wsp32.p + h->wsp_base, 0, sizeof(float) * h->wsp_len));
     }
     const int64_t Nx = h->Nx, Ny = h->Ny, N = h->N;
     h->ld = ((h->n_if + 63) / 64) * 64;

@@ -282,10 +282,13 @@ def test_solve_c1_tight_matches_global_lu(gpu_lib):
     assert rel_res < 1e-10
 
 
-def test_solve_c1_fp32_refined(gpu_lib):
-    """FP32 sweeps with FP64 residual refinement reach the FP64 answer."""
+@pytest.mark.parametrize("layout", [0] + LAYOUTS)
+def test_solve_c1_fp32_refined(gpu_lib, layout):
+    """FP32 sweeps with FP64 residual refinement reach the FP64 answer (FP32
+    and FP64 sweeps alternate on one handle: for STREAM they must not share
+    workspace bytes)."""
     W = gpu_lib
-    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-6)
+    wl, h, Xl, Yl, dec, X, Y = _c1_pair(W, precision=1, tau_in=1e-6, layout=layout)
     u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol)
     W.dd_destroy(h)
     u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
