@@ -41,6 +41,11 @@ def kernel_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def flops_per_update(P):
     """Algorithmic FLOP of one DOF-update (one leapfrog step of one node):
     stiffness 4(P+2) + 3, p update 2, velocity update 7, filter 4."""
@@ -120,7 +125,7 @@ def variants(W, wl, u_ref, _unused, steps=2):
     return out
 
 
-BYTES_STREAM = {"fp64": 72, "fp32": 36}   # per DOF-update, STREAM layout (9 words)
+BYTES_STREAM = {"fp64": 80, "fp32": 40}   # per DOF-update, STREAM layout (10 words)
 
 
 def batch_bench(args):
@@ -144,8 +149,10 @@ def batch_bench(args):
     setup_s = time.perf_counter() - t0
     tol = wls[0].tol
     fs = [s_["f"] for s_ in specs]
+    log(f"batch setup {setup_s:.1f} s, {len(specs)} problems")
     for _ in range(args.warmup):
         W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True)
+        log("warm-up batch done")
     lat, rounds, res = [], [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -154,6 +161,7 @@ def batch_bench(args):
         lat.append(time.perf_counter() - t1)
         rounds.append(W.dd_batch_launches(b))
         res = (us, sts, rcs)
+        log(f"batch solve: {lat[-1]:.3f} s, {rounds[-1]} launch rounds")
     total = time.perf_counter() - t0
     us, sts, rcs = res
     dof = sum(st["dof_updates"] for st in sts) * args.steps
@@ -228,8 +236,11 @@ def serve_bench(args):
                     if dt > 0:
                         time.sleep(dt)
                 ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 2000))
-            res = [W.dd_engine_wait(e, rid, s_["c"].size, allow_notconv=True)
-                   for rid, s_ in zip(ids, specs)]
+            res = []
+            for k, (rid, s_) in enumerate(zip(ids, specs)):
+                res.append(W.dd_engine_wait(e, rid, s_["c"].size, allow_notconv=True))
+                log(f"request {k} ({s_['c'].size} nodes, P={s_['P']}) done: "
+                    f"{res[-1][2][2] - res[-1][2][0]:.3f} s")
             wall = time.perf_counter() - t0
             info = W.dd_engine_get_info(e)
         finally:
@@ -335,15 +346,18 @@ def main():
                                    allow_notconv=True)
         return st
 
+    log(f"setup {setup_s:.1f} s, layout {W.dd_layout(h)}")
     for _ in range(args.warmup):
         one()
+        log("warm-up solve done")
     torch.cuda.synchronize()
     lat, stats = [], []
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         t1 = time.perf_counter()
         stats.append(one())
         lat.append(time.perf_counter() - t1)
+        log(f"solve {k}: {lat[-1]:.3f} s, {stats[-1]['outer_iters']} outer iterations")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 

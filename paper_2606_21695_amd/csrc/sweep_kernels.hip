@@ -26,7 +26,9 @@
 //    with zero padding, so the (2P+1)-point 1D windows need no bounds
 //    checks (one barrier per step).
 //  * STREAM: any subdomain size; the NODE arithmetic with the state in
-//    device memory (zero-padded p grids, one barrier per step).
+//    device memory (zero-padded p grids, one barrier per step); waves walk
+//    up column segments with the Y windows in registers and exchange X
+//    neighbours across lanes.
 // Both stage the per-step filter / forcing tables of the subdomain in LDS
 // (broadcast reads) when the subdomain starts.
 #include "wavedd_internal.h"
@@ -1311,6 +1313,9 @@ __global__ void __launch_bounds__(kMaxWG) apply_node_kernel(const SweepArgs<Real
 // LDS (after 40 doubles for reductions): window table (kMaxP+2) x
 // (2 kMaxP+1), reference element matrix, per-step tables.
 constexpr int kStreamWT = (kMaxP + 2) * (2 * kMaxP + 1);
+// Workgroup bound: two waves per SIMD leave 256 registers per lane for the
+// column windows, the X neighbours in flight and the state addresses.
+constexpr int kStreamWG = 512;
 constexpr int kStreamTab = (kStreamWT + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
 
 // Window class of local node k on a line of nl nodes: 1..P-1 element
@@ -1338,6 +1343,160 @@ __device__ __forceinline__ void stream_tables(Real* lds, const double (*K1)[kMax
     }
 }
 
+// Cross-lane read of a value held by another lane of the wave (lane index
+// taken modulo 64).
+__device__ __forceinline__ double shfl_real(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ float shfl_real(float v, int src) { return __shfl(v, src, 64); }
+
+// Work split of the STREAM step loop: wave w takes column group w % CG and
+// row segment w / CG.  A column group spans 64 lanes over columns
+// g*(64-2P) - P + lane; the P lanes at each end only supply neighbour
+// values for the X windows (by cross-lane reads), the others own their
+// column's nodes in the segment and walk up it with the Y window in
+// registers.
+template <typename Real, int P>
+struct StreamGeom {
+    int lane, i, ic, pcol, j0, j1;
+    bool active, colv, own;
+    Real wx[2 * P + 1];
+
+    __device__ void setup(int nxl, int nyl, const Real* WT) {
+        constexpr int OW = 64 - 2 * P;
+        const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+        lane = tid & 63;
+        const int CG = (nxl + OW - 1) / OW;
+        const int RS = nwaves / CG;
+        const int g = wave % CG, r = wave / CG;
+        const int RL = RS > 0 ? (nyl + RS - 1) / RS : 0;
+        j0 = r * RL;
+        j1 = min(nyl, j0 + RL);
+        active = r < RS && j0 < j1;
+        if (!active) j0 = j1 = 0;
+        i = g * OW - P + lane;
+        ic = min(max(i, 0), nxl - 1);
+        colv = i >= -kMaxP && i < nxl + kMaxP;
+        own = active && lane >= P && lane < 64 - P && i >= 0 && i < nxl;
+        pcol = colv ? i + kMaxP : 0;
+        const Real* w = WT + stream_class<P>(own ? i : 1, nxl) * (2 * P + 1);
+#pragma unroll
+        for (int k = 0; k <= 2 * P; ++k) wx[k] = w[k];
+    }
+};
+
+// Rows of the STREAM step loop kept in flight per wave (loads issued this
+// many rows ahead of their use, so each wave has several rows of memory
+// traffic outstanding).
+template <typename Real>
+constexpr int stream_ahead() { return sizeof(Real) == 8 ? 2 : 3; }
+
+// Node record of the STREAM workspace (kStreamRec Reals per node): the
+// state quad {pd, vr, vi, alpha} and the coefficient quad {betaX, betaY,
+// beta Re b, beta Im b}.  A step reads both quads and writes the state quad.
+constexpr int kStreamRec = kStreamRecord;
+template <typename Real>
+struct alignas(4 * sizeof(Real)) Quad {
+    Real a, b, c, d;
+};
+
+// One row's loads of one lane: p entering the Y window (row j + P) and the
+// node record at row j.  The loads are unconditional (addresses clamped to
+// the segment and the grid, values of lanes or rows outside selected away),
+// so no branch separates a load from its use and the wait counts let the
+// rows ahead stay in flight.
+template <typename Real>
+struct StreamRow {
+    Real pn;
+    Quad<Real> st, cf;
+};
+
+template <typename Real, int P>
+__device__ __forceinline__ void stream_fetch(StreamRow<Real>& r, const StreamGeom<Real, P>& G,
+                                             const Real* cur, int stride, int j, int nxl,
+                                             const Real* NS) {
+    const bool inrow = j < G.j1;
+    const int jc = inrow ? j : G.j1 - 1;
+    const Real pn = cur[(jc + P + kMaxP) * stride + G.pcol];
+    r.pn = (G.colv && inrow) ? pn : Real(0);
+    const Real* rec = NS + (size_t)kStreamRec * (jc * nxl + G.ic);
+    r.st = *reinterpret_cast<const Quad<Real>*>(rec);
+    r.cf = *reinterpret_cast<const Quad<Real>*>(rec + 4);
+}
+
+// One step of the STREAM layout for the column segment of this lane: walk
+// up the rows with the Y window in registers, X neighbours from the lanes
+// beside, loads issued stream_ahead rows early.  The body has no branch
+// around a load (only the stores are predicated), so the waits keep the
+// rows ahead in flight.  LAST: the step that ends a WaveHoltz iteration
+// writes u = (2/N_t) v and accumulates the fixed-point residual instead.
+template <typename Real, int P, bool LAST>
+__device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const Real* cur, Real* nxt,
+                                            int stride, int nxl, int nyl, Real* NS, const Real* WT,
+                                            const Quad<Real> tb, Real sig, const SweepArgs<Real>& A,
+                                            const SubDesc& d, bool has_old, double& dsum,
+                                            double& nsum) {
+    constexpr int W = 2 * P + 1;
+    constexpr int kAhead = stream_ahead<Real>();
+    Real win[W];
+    win[0] = Real(0);
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const Real v = cur[(G.j0 - P + k + kMaxP) * stride + G.pcol];
+        win[k + 1] = G.colv ? v : Real(0);
+    }
+    StreamRow<Real> R[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) stream_fetch(R[q], G, cur, stride, G.j0 + q, nxl, NS);
+    for (int jb = G.j0; jb < G.j1; jb += kAhead) {
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q) {
+            const int j = jb + q;
+            const StreamRow<Real> r = R[q];
+            stream_fetch(R[q], G, cur, stride, j + kAhead, nxl, NS);
+#pragma unroll
+            for (int k = 0; k < 2 * P; ++k) win[k] = win[k + 1];
+            win[2 * P] = r.pn;
+            const Real p = win[P];
+            const Real* wy = WT + stream_class<P>(min(j, nyl - 1), nyl) * W;
+            Real X = Real(0), Y = Real(0);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const Real nb = k == P ? p : shfl_real(p, G.lane - P + k);
+                X = fma(G.wx[k], nb, X);
+                Y = fma(wy[k], win[k], Y);
+            }
+            Real t = r.cf.c * tb.a;
+            t = fma(r.cf.d, tb.b, t);
+            t = fma(-r.cf.a, X, t);
+            t = fma(-r.cf.b, Y, t);
+            const Real pd = fma(r.st.d, r.st.a, t);
+            const Real vr = fma(tb.c, p, r.st.b);
+            const Real vi = fma(tb.d, pd, r.st.c);
+            const bool put = G.own && j < G.j1;
+            const int n = j * nxl + G.i;
+            if (!LAST) {
+                if (put) {
+                    *reinterpret_cast<Quad<Real>*>(NS + (size_t)kStreamRec * n) =
+                        Quad<Real>{pd, vr, vi, r.st.d};
+                    nxt[(j + kMaxP) * stride + G.pcol] = fma(sig, pd, p);
+                }
+            } else if (put) {
+                // u_new = (2/N_t) v (eq. (7)); fixed-point residual sums
+                const double ur = d.two_over_nt * (double)vr;
+                const double ui = d.two_over_nt * (double)vi;
+                double orr = 0.0, oi = 0.0;
+                if (has_old) {
+                    const double2 o = A.u[d.node_off + n];
+                    orr = o.x;
+                    oi = o.y;
+                }
+                dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+                nsum += ur * ur + ui * ui;
+                A.u[d.node_off + n] = make_double2(ur, ui);
+            }
+        }
+    }
+}
+
 template <typename Real, int P, bool HAS_SRC>
 __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
                                   double* red) {
@@ -1351,28 +1510,26 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const Real* TAB = lds + kStreamTab;
     Real* p0 = A.ws_p + d.ws_off;
     Real* p1 = p0 + stream_pad_nodes(nxl, nyl);
-    Real* PD = A.ws_s + d.node_off;
-    Real* VR = PD + A.ws_stride;
-    Real* VI = VR + A.ws_stride;
-    Real* BR = VI + A.ws_stride;
-    Real* BI = BR + A.ws_stride;
+    Real* NS = A.ws_s + (size_t)kStreamRec * d.node_off;
     const Real* AL = A.coef.alpha + d.node_off;
-    const Real* BX = A.coef.betaX + d.node_off;
-    const Real* BY = A.coef.betaY + d.node_off;
     // beta * b (eq. (4) right-hand side with the interface data)
     {
         int il = tid % nxl, jl = tid / nxl;
         for (int n = tid; n < nloc; n += bd) {
             const double be = (double)A.coef.beta[d.node_off + n];
             const double2 b = assemble_b(A, d, il, jl);
-            BR[n] = (Real)(be * b.x);
-            BI[n] = (Real)(be * b.y);
+            Real* rec = NS + (size_t)kStreamRec * n;
+            *reinterpret_cast<Quad<Real>*>(rec + 4) =
+                Quad<Real>{A.coef.betaX[d.node_off + n], A.coef.betaY[d.node_off + n],
+                           (Real)(be * b.x), (Real)(be * b.y)};
             il += di;
             jl += dj;
             if (il >= nxl) { il -= nxl; ++jl; }
         }
     }
     __syncthreads();
+    StreamGeom<Real, P> G;
+    G.setup(nxl, nyl, WT);
     const Real sig = (Real)d.sigma;
     const int nt = d.nt;
     int it = 0;
@@ -1390,9 +1547,8 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
                     p = (Real)u.x;
                     pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
                 }
-                VR[n] = k0 * p;
-                VI[n] = kh0 * pd;
-                PD[n] = pd;
+                *reinterpret_cast<Quad<Real>*>(NS + (size_t)kStreamRec * n) =
+                    Quad<Real>{pd, k0 * p, kh0 * pd, AL[n]};
                 p1[(jl + kMaxP) * stride + il + kMaxP] = fma(sig, pd, p);
                 il += di;
                 jl += dj;
@@ -1404,59 +1560,14 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             __syncthreads();
             const Real* cur = (nu & 1) ? p1 : p0;
             Real* nxt = (nu & 1) ? p0 : p1;
-            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
-            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
-            const bool last = nu == nt - 1;
-            int il = tid % nxl, jl = tid / nxl;
-#pragma nounroll
-            for (int n = tid; n < nloc; n += bd) {
-                const int pidx = (jl + kMaxP) * stride + il + kMaxP;
-                const Real* wx = WT + stream_class<P>(il, nxl) * W;
-                const Real* wy = WT + stream_class<P>(jl, nyl) * W;
-                Real X = Real(0), Y = Real(0);
-#pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    X = fma(wx[j], cur[pidx + j - P], X);
-                    Y = fma(wy[j], cur[pidx + (j - P) * stride], Y);
-                }
-                const Real p = cur[pidx];
-                const bool bnd = il == 0 || il == nxl - 1 || jl == 0 || jl == nyl - 1;
-                Real al = Real(1), br = Real(0), bi = Real(0);
-                if (bnd) al = AL[n];
-                if (HAS_SRC || bnd) {
-                    br = BR[n];
-                    bi = BI[n];
-                }
-                Real t = br * c;
-                t = fma(bi, sv, t);
-                t = fma(-BX[n], X, t);
-                t = fma(-BY[n], Y, t);
-                const Real pd = fma(al, PD[n], t);
-                const Real vr = fma(k1, p, VR[n]);
-                const Real vi = fma(k2, pd, VI[n]);
-                if (!last) {
-                    PD[n] = pd;
-                    VR[n] = vr;
-                    VI[n] = vi;
-                    nxt[pidx] = fma(sig, pd, p);
-                } else {
-                    // u_new = (2/N_t) v (eq. (7)); fixed-point residual sums
-                    const double ur = d.two_over_nt * (double)vr;
-                    const double ui = d.two_over_nt * (double)vi;
-                    double orr = 0.0, oi = 0.0;
-                    if (m > 0) {
-                        const double2 o = A.u[d.node_off + n];
-                        orr = o.x;
-                        oi = o.y;
-                    }
-                    dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
-                    nsum += ur * ur + ui * ui;
-                    A.u[d.node_off + n] = make_double2(ur, ui);
-                }
-                il += di;
-                jl += dj;
-                if (il >= nxl) { il -= nxl; ++jl; }
-            }
+            if (!G.active) continue;
+            const Quad<Real> tb{TAB[4 * nu + 0], TAB[4 * nu + 1], TAB[4 * nu + 2], TAB[4 * nu + 3]};
+            if (nu < nt - 1)
+                stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, NS, WT, tb, sig, A, d,
+                                            m > 0, dsum, nsum);
+            else
+                stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, NS, WT, tb, sig, A, d,
+                                           m > 0, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
         it = m + 1;
@@ -1470,7 +1581,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
 }
 
 template <typename Real, int P, bool HAS_SRC>
-__global__ void __launch_bounds__(kMaxWG) sweep_stream_kernel(const SweepArgs<Real> A) {
+__global__ void __launch_bounds__(kStreamWG) sweep_stream_kernel(const SweepArgs<Real> A) {
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
@@ -1669,7 +1780,7 @@ template <typename Real>
 hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
     const size_t lds = a.lds_bytes;
     const bool src = a.Fre != nullptr && a.src != 0.0;
-    if (wg > kMaxWG) return hipErrorInvalidValue;
+    if (wg > kStreamWG) return hipErrorInvalidValue;
 #define L(PP)                                                                                    \
     if (src)                                                                                     \
         hipLaunchKernelGGL((sweep_stream_kernel<Real, PP, true>), dim3(a.n_items), dim3(wg), lds, \

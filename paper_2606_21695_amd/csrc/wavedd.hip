@@ -426,7 +426,7 @@ int patch_threads(const dd_handle* h) {
 
 int layout_threads(const dd_handle* h, int layout) {
     int t = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl : patch_threads(h);
-    if (layout == DD_LAYOUT_STREAM) t = (int)std::min<int64_t>(1024, h->nloc);
+    if (layout == DD_LAYOUT_STREAM) t = (int)std::min<int64_t>(512, h->nloc);
     return ((t + 63) / 64) * 64;
 }
 
@@ -447,7 +447,12 @@ void layout_config(dd_handle* h, int layout) {
 // Fits in one workgroup for every precision the handle carries (FP64
 // always, for the refinement residuals of FP32 handles too).
 bool layout_fits(const dd_handle* h, int layout) {
-    if (layout == DD_LAYOUT_STREAM) return layout_lds(h, layout, DD_FP64) <= kLdsLimit;
+    if (layout == DD_LAYOUT_STREAM) {
+        // every column group of the step loop needs a wave of its own
+        const int ow = 64 - 2 * h->P, groups = (h->nxl + ow - 1) / ow;
+        return groups <= layout_threads(h, layout) / 64 &&
+               layout_lds(h, layout, DD_FP64) <= kLdsLimit;
+    }
     const bool threads_ok = layout == DD_LAYOUT_NODE ? h->nxl * h->nyl <= 1024 : patch_threads(h) <= 512;
     return threads_ok && layout_lds(h, layout, DD_FP64) <= kLdsLimit;
 }
@@ -1413,12 +1418,12 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
     bytes += cit * (sizeof(wdd::SubDesc) + 4) + cw * 8 + ci * 20 + cn * 28;
     if (cwsp > 0) {
         STCHK(S->d_wsp.alloc(cwsp));
-        STCHK(S->d_wss.alloc(5 * cn));
-        bytes += 8 * (cwsp + 5 * cn);
+        STCHK(S->d_wss.alloc(wdd::kStreamRecord * cn));
+        bytes += 8 * (cwsp + wdd::kStreamRecord * cn);
         if (fp32) {
             STCHK(S->d_wsp32.alloc(cwsp));
-            STCHK(S->d_wss32.alloc(5 * cn));
-            bytes += 4 * (cwsp + 5 * cn);
+            STCHK(S->d_wss32.alloc(wdd::kStreamRecord * cn));
+            bytes += 4 * (cwsp + wdd::kStreamRecord * cn);
         }
     }
     STCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));

@@ -10,6 +10,7 @@ namespace wdd {
 
 constexpr int kMaxP = 4;           // largest supported polynomial degree
 constexpr int kMaxWG = 1024;       // largest workgroup
+constexpr int kStreamRecord = 8;   // Reals per node of the STREAM workspace
 
 // One subdomain work item of a sweep launch.  All offsets index the
 // per-node arrays (node_off) or the interface arrays (if_off, nbr_off).
@@ -61,8 +62,8 @@ struct SweepArgs {
     double tau;              // inner tolerance (<= 0: fixed count)
     int max_wh;              // iteration cap / fixed count
     Real* ws_p;              // STREAM layout: padded p grids (2 per subdomain, at desc.ws_off)
-    Real* ws_s;              // STREAM layout: pd, vr, vi, beta*Re b, beta*Im b (node-indexed)
-    int64_t ws_stride;       // distance between those five arrays
+    Real* ws_s;              // STREAM layout: kStreamRecord Reals per node (node-indexed)
+    int64_t ws_stride;       // node capacity of ws_s
     size_t lds_bytes;        // dynamic LDS per workgroup of the launch
     int nt_max;              // largest N_t of the launch (sizes the LDS tables)
     double K1[kMaxP + 1][kMaxP + 1][kMaxP + 1];  // K1[P][a][b]: reference D^T W D

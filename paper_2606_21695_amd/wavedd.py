@@ -480,12 +480,7 @@ class Problem:
         o = dd_default_options(precision=precision, layout=layout,
                                tau_in=wl.tau_in if tau_in is None else tau_in, **opt)
         # sample the wavespeed at the library's own node coordinates
-        probe = dd_setup(wl.nx, wl.ny, wl.P, np.ones((wl.nx * wl.P + 1) * (wl.ny * wl.P + 1)),
-                         wl.omega, wl.sx, wl.sy, wl.x0, wl.x1, wl.y0, wl.y1, o)
-        try:
-            self.X, self.Y = dd_node_coords(probe)
-        finally:
-            dd_destroy(probe)
+        self.X, self.Y = dd_mesh_coords(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
         self.c = np.asarray(wl.c(self.X, self.Y), dtype=float)
         self.f = np.asarray(wl.f(self.X, self.Y), dtype=float)
         self.h = dd_setup(wl.nx, wl.ny, wl.P, self.c, wl.omega, wl.sx, wl.sy, wl.x0, wl.x1,

@@ -180,7 +180,7 @@ def test_stream_solve_large_subdomains_matches_oracle_dd(gpu_lib):
     h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, tau_in=1e-12)
     dec, X, Y = _oracle(nx, ny, P, sx, sy, om, _cwave)
     lay, wg = W.dd_layout(h)
-    assert lay == 4 and wg == 1024
+    assert lay == 4 and wg == 512
 
     def src(X, Y):
         return np.exp(-((X - 0.37) ** 2 + (Y - 0.58) ** 2) / (2 * 0.04 ** 2))
