@@ -145,20 +145,26 @@ def batch_bench(args):
         tau = args.tau_in
     t0 = time.perf_counter()
     b = W.dd_batch_setup(specs, W.dd_default_options(precision=prec, tau_in=tau,
-                                                     relax=args.relax))
+                                                     relax=args.relax, max_wh=args.max_wh))
     setup_s = time.perf_counter() - t0
     tol = wls[0].tol
     fs = [s_["f"] for s_ in specs]
     log(f"batch setup {setup_s:.1f} s, {len(specs)} problems")
+    def solve_logged(tag):
+        """One batched solve; each problem's completion is reported as it
+        happens."""
+        t1 = time.perf_counter()
+        r = W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True, progress=lambda k: log(
+            f"{tag}: {k}/{len(fs)} problems done at {time.perf_counter() - t1:.1f} s"))
+        return r, time.perf_counter() - t1
+
     for _ in range(args.warmup):
-        W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True)
-        log("warm-up batch done")
+        solve_logged("warm-up")
     lat, rounds, res = [], [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        t1 = time.perf_counter()
-        us, sts, rcs, rc = W.dd_batch_solve(b, fs, tol, 2000, allow_notconv=True)
-        lat.append(time.perf_counter() - t1)
+        (us, sts, rcs, rc), el = solve_logged("timed")
+        lat.append(el)
         rounds.append(W.dd_batch_launches(b))
         res = (us, sts, rcs)
         log(f"batch solve: {lat[-1]:.3f} s, {rounds[-1]} launch rounds")
@@ -188,12 +194,13 @@ def batch_bench(args):
         "config": {"workload": f"c4: {len(wls)} independent problems, "
                                f"{sum(wl.sx * wl.sy for wl in wls)} subdomains, P in 1..4, "
                                f"omega={wls[0].omega}, tol={tol}",
-                   "precision": args.precision, "tau_in": tau, "relax": args.relax},
+                   "precision": args.precision, "tau_in": tau, "relax": args.relax,
+                   "max_wh": args.max_wh},
         "problems": len(wls),
         "solves_per_s": len(wls) * args.steps / total,
         "batch_latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                              "p99": 1e3 * float(np.percentile(lat, 99))},
-        "launch_rounds": rounds[-1],
+        "launches": rounds[-1],
         "not_converged": int(sum(r != 0 for r in rcs)),
         "rel_residual_global_max": float(max(rel)),
         "setup_s": setup_s,
@@ -218,11 +225,14 @@ def serve_bench(args):
     from paper_2606_21695_amd import wavedd as W
     W.require_gpu()
     torch.cuda.set_device(0)
-    wls = workloads.c5(n_requests=args.requests)
+    # the first requests of the stream whose global mesh has at most
+    # --max-nodes nodes (bounded bench time)
+    wls = [wl for wl in workloads.c5(n_requests=20 * args.requests)
+           if (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1) <= args.max_nodes][:args.requests]
     specs = [W.workload_spec(wl) for wl in wls]
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
     o = W.dd_default_options(precision=prec, tau_in=wls[0].tau_in if prec == W.DD_FP32 else 1e-10,
-                             relax=args.relax)
+                             relax=args.relax, max_wh=args.max_wh)
     budget = int(args.budget_gib * (1 << 30))
 
     def run(arrivals):
@@ -236,11 +246,14 @@ def serve_bench(args):
                     if dt > 0:
                         time.sleep(dt)
                 ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 2000))
-            res = []
-            for k, (rid, s_) in enumerate(zip(ids, specs)):
-                res.append(W.dd_engine_wait(e, rid, s_["c"].size, allow_notconv=True))
-                log(f"request {k} ({s_['c'].size} nodes, P={s_['P']}) done: "
-                    f"{res[-1][2][2] - res[-1][2][0]:.3f} s")
+            res = [None] * len(ids)
+            where = {rid: k for k, rid in enumerate(ids)}
+            for _ in ids:
+                rid = W.dd_engine_wait_any(e)
+                k = where[rid]
+                res[k] = W.dd_engine_wait(e, rid, specs[k]["c"].size, allow_notconv=True)
+                log(f"request {k} ({specs[k]['c'].size} nodes, P={specs[k]['P']}) done: "
+                    f"{res[k][2][2] - res[k][2][0]:.3f} s")
             wall = time.perf_counter() - t0
             info = W.dd_engine_get_info(e)
         finally:
@@ -261,8 +274,8 @@ def serve_bench(args):
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == W.DD_FP64 else "f32 sweep / f64 outer",
         "data": "synthetic (seeded request stream: own mesh, P, omega, wavespeed, sources)",
-        "config": {"workload": f"c5: first {len(specs)} requests, Poisson arrivals at "
-                               f"rho={args.rho} of saturated throughput",
+        "config": {"workload": f"c5: first {len(specs)} requests of <= {args.max_nodes} nodes, "
+                               f"Poisson arrivals at rho={args.rho} of saturated throughput",
                    "precision": args.precision, "max_active": args.max_active,
                    "budget_gib": args.budget_gib},
         "saturated_solves_per_s": mu,
@@ -271,7 +284,7 @@ def serve_bench(args):
         "saturated_latency_ms": {"p50": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 50)),
                                  "p99": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 99))},
         "dof_updates_per_s": dof / wall,
-        "launch_rounds": info["launches"],
+        "launches": info["launches"],
         "peak_running": info["peak_running"],
         "not_converged": int(sum(rc != 0 for *_, rc in res)),
         "request_sizes": {"nodes_min": int(min(s_["c"].size for s_ in specs)),
@@ -294,7 +307,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
     ap.add_argument("--serve", action="store_true", help="serving engine on the c5 stream")
+    ap.add_argument("--max-wh", type=int, default=1000,
+                    help="WaveHoltz cap per subdomain solve for the batch / serving modes "
+                         "(large subdomains need hundreds of periods)")
     ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--max-nodes", type=int, default=600000,
+                    help="serving mode: skip requests with more global nodes")
     ap.add_argument("--rho", type=float, default=0.8)
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--budget-gib", type=float, default=64.0)

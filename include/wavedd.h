@@ -224,10 +224,13 @@ int dd_mesh_coords(const dd_mesh* mesh, int degree, double* x, double* y);
  * (Sec. III), so subdomains of different problems can share one launch just
  * as the subdomains of one problem do (Sec. VI: all subdomains of a sweep in
  * one kernel launch).  A batch places its problems in one device store; each
- * problem runs its own FP64 outer iteration, and every round of sweeps is a
- * batched launch per launch configuration (precision, degree, layout,
- * workgroup class) whose work list is ordered by estimated cost (DOFs x
- * (N_t - 1) x WaveHoltz iterations of the previous sweep), longest first.
+ * problem runs its own FP64 outer iteration on its own host thread and posts
+ * its sweeps; whenever one of four launch slots is free, every pending sweep
+ * goes into one batched launch (per launch configuration: precision, degree,
+ * layout, workgroup class) whose work list is ordered by estimated cost
+ * (DOFs x (N_t - 1) x WaveHoltz iterations of the previous sweep), longest
+ * first.  Sweeps posted while the slots are busy form the next batch, so
+ * batches grow with the load and no problem waits for another's sweep.
  * Layouts are autotuned once per subdomain shape (mx, my, P, precision).
  * ------------------------------------------------------------------------ */
 typedef struct dd_batch dd_batch;
@@ -269,7 +272,21 @@ int dd_batch_solve(dd_batch* b, const double* const* f_re, const double* const* 
 int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, double* dof_updates,
                         int* launches);
 
-/* Batched launch rounds issued by the last dd_batch_solve. */
+/* dd_batch_solve in two calls: _start validates, launches the problems'
+ * solves on host threads and returns; every array passed must stay valid
+ * until _finish, which waits for them and returns what dd_batch_solve would.
+ * One solve per batch at a time (DD_EINVAL otherwise). */
+int dd_batch_solve_start(dd_batch* b, const double* const* f_re, const double* const* f_im,
+                         double tol, int max_iter, double* const* u_re, double* const* u_im,
+                         dd_stats* st, int* rc);
+int dd_batch_solve_finish(dd_batch* b);
+
+/* Between _start and _finish: block until more than `seen` problems have
+ * finished (or all have); *finished receives the count.  Returns at once
+ * when no solve is running. */
+int dd_batch_wait_progress(dd_batch* b, int seen, int* finished);
+
+/* Batched launches issued by the last dd_batch_solve. */
 int dd_batch_launches(const dd_batch* b, int64_t* launches);
 
 /* ------------------------------------------------------------------------
@@ -282,9 +299,9 @@ int dd_batch_launches(const dd_batch* b, int64_t* launches);
  * store holding every admitted problem's sweep arrays (ranges handed out by
  * a first-fit allocator), the rest pays for the per-request outer-iteration
  * vectors.  Each running request advances its own FP64 outer iteration on
- * its own host thread and stream; every round of sweeps is one batched
- * launch over all running requests' subdomains (as for dd_batch_solve), and
- * requests join and retire between rounds.  Results stay with the engine
+ * its own host thread and stream; its sweeps share batched launches with
+ * the other running requests' (as for dd_batch_solve), and requests join and
+ * retire between launches.  Results stay with the engine
  * until dd_engine_wait collects them.
  * ------------------------------------------------------------------------ */
 typedef struct dd_engine dd_engine;
@@ -295,7 +312,7 @@ typedef struct dd_engine dd_engine;
 
 typedef struct {
     int64_t queued, running, done;   /* requests in each state */
-    int64_t launches;                /* batched launch rounds so far */
+    int64_t launches;                /* batched launches so far */
     int64_t peak_running;
     size_t budget_bytes;             /* as given */
     size_t store_bytes;              /* device store */
@@ -327,6 +344,11 @@ int dd_engine_status(dd_engine* e, int64_t id, int* state);
  * Returns the request's own code (DD_OK, DD_ENOTCONV, ...). */
 int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stats* st,
                    double* times);
+
+/* Block until some submitted, not yet collected request is done; *id
+ * receives it (collect it with dd_engine_wait).  DD_EINVAL if none is
+ * outstanding. */
+int dd_engine_wait_any(dd_engine* e, int64_t* id);
 
 int dd_engine_get_info(dd_engine* e, dd_engine_info* info);
 

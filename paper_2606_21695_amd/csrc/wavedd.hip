@@ -257,14 +257,18 @@ struct SweepReq {
     int rc = 0;
 };
 
-// Rendezvous of the problems solving concurrently on one store: each
-// problem's host thread posts its sweep and blocks; once every active
-// problem has posted, the last one launches all posted sweeps together.
+// Continuous batching of the sweeps of the problems solving concurrently on
+// one store: a problem posts its sweep and blocks; whenever a launch slot is
+// free, the posting thread takes every pending sweep into one batched
+// launch on that slot's stream.  While launches run, new posts queue up and
+// form the next batch, so the batches grow with the load and no problem
+// waits for another's sweep to finish.
 struct Sched {
+    static constexpr int kSlots = 4;   // launches in flight (one stream each)
     std::mutex mu;
     std::condition_variable cv;
-    int active = 0;
-    bool launching = false;
+    int active = 0;                    // problems inside a batched solve
+    bool busy[kSlots] = {};
     std::vector<SweepReq*> pending;
     std::atomic<int64_t> launches{0};
     std::string err;
@@ -295,15 +299,14 @@ struct Store {
     DBuf<float> d_wsp32, d_wss32;    // STREAM layout workspace, FP32 sweeps (own bytes: FP64 and
                                      // FP32 sweeps of different problems run concurrently)
     DBuf<double2> d_gin, d_gout;     // shared: per-problem sweep input / output ranges
-    DBuf<wdd::SubDesc> d_work;       // shared: work lists of batched launches
+    DBuf<wdd::SubDesc> d_work;       // shared: work lists of batched launches (per slot)
     DBuf<int> d_work_iters;
-    wdd::SubDesc* h_work = nullptr;  // pinned staging of the work lists
+    wdd::SubDesc* h_work = nullptr;  // pinned staging of the work lists (per slot)
     int* h_work_iters = nullptr;
     hipStream_t stream = nullptr;
-    static constexpr int kGroupStreams = 4;
-    hipStream_t gs[kGroupStreams] = {};
-    hipEvent_t ev_in = nullptr, ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t gev[kGroupStreams] = {};
+    hipStream_t ss[Sched::kSlots] = {};   // launch slot streams
+    hipEvent_t sev0[Sched::kSlots] = {}, sev1[Sched::kSlots] = {};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t bytes = 0;
     std::mutex mu;            // allocators, layout cache
     std::map<std::tuple<int, int, int, int>, int> layout_cache;  // (mx, my, P, prec) -> layout
@@ -563,7 +566,7 @@ double item_cost(const dd_handle* h, int64_t l) {
 // source); each group is one launch whose work list is sorted by cost,
 // longest first (the hardware dispatches workgroups in order, so the list
 // is the schedule).  Groups run concurrently on the store's group streams.
-int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, double* ms_out = nullptr,
+int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double* ms_out = nullptr,
                  int* groups_out = nullptr) {
     HIPCHK(hipSetDevice(S->dev));
     struct Item {
@@ -599,6 +602,10 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, double* ms_out = 
         gg.nt_max = std::max(gg.nt_max, h->nt_max);
         for (int64_t l = 0; l < h->L; ++l) gg.items.push_back({item_cost(h, l), r, l});
     }
+    wdd::SubDesc* hw = S->h_work + (int64_t)slot * S->cap_item;
+    int* hi = S->h_work_iters + (int64_t)slot * S->cap_item;
+    wdd::SubDesc* dw = S->d_work.p + (int64_t)slot * S->cap_item;
+    int* di = S->d_work_iters.p + (int64_t)slot * S->cap_item;
     int64_t total = 0;
     for (const auto& kv : groups) total += (int64_t)kv.second.items.size();
     if (total > S->cap_item) return fail(DD_EINVAL, "batched work list exceeds the store");
@@ -614,98 +621,65 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, double* ms_out = 
             wdd::SubDesc d = q->h->desc[it.l];
             d.max_wh = q->max_wh;
             d.tau = q->tau;
-            S->h_work[total + (int64_t)i] = d;
+            hw[total + (int64_t)i] = d;
         }
         for (const Item& it : g.items)
             g.lds = std::max(g.lds, lds_for(reqs[it.r]->h, g.prec, g.wg, g.nt_max));
         total += (int64_t)g.items.size();
     }
-    hipStream_t s = S->stream;
-    HIPCHK(hipEventRecord(S->ev0, s));
-    HIPCHK(hipMemcpyAsync(S->d_work.p, S->h_work, sizeof(wdd::SubDesc) * total,
-                          hipMemcpyHostToDevice, s));
+    hipStream_t s = S->ss[slot];
+    HIPCHK(hipEventRecord(S->sev0[slot], s));
+    HIPCHK(hipMemcpyAsync(dw, hw, sizeof(wdd::SubDesc) * total, hipMemcpyHostToDevice, s));
     for (const SweepReq* q : reqs)
         HIPCHK(hipMemcpyAsync(S->d_gin.p + q->h->if_base, q->g_in, sizeof(double2) * q->h->n_if,
                               hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipEventRecord(S->ev_in, s));
     const double(*K1)[wdd::kMaxP + 1][wdd::kMaxP + 1] = reqs[0]->h->K1all;
     int gi = 0;
-    bool used[Store::kGroupStreams] = {};
     for (auto& kv : groups) {
         Group& g = kv.second;
         if (g.items.empty()) continue;
-        const int k = gi++ % Store::kGroupStreams;
-        hipStream_t gs = S->gs[k];
-        if (!used[k]) HIPCHK(hipStreamWaitEvent(gs, S->ev_in, 0));
-        used[k] = true;
+        ++gi;
         const bool wf = g.src != 0.0;
         hipError_t e;
         if (g.prec == DD_FP32) {
             auto a = store_args<float>(S, S->d_gin.p, S->d_gout.p, g.src, wf, 0.0, 1, K1);
-            a.desc = S->d_work.p + g.off;
+            a.desc = dw + g.off;
             a.n_items = (int)g.items.size();
-            a.wh_iters = S->d_work_iters.p + g.off;
+            a.wh_iters = di + g.off;
             a.lds_bytes = g.lds;
             a.nt_max = g.nt_max;
-            e = launch_layout<float>(g.layout, a, g.P, g.wg, gs);
+            e = launch_layout<float>(g.layout, a, g.P, g.wg, s);
         } else {
             auto a = store_args<double>(S, S->d_gin.p, S->d_gout.p, g.src, wf, 0.0, 1, K1);
-            a.desc = S->d_work.p + g.off;
+            a.desc = dw + g.off;
             a.n_items = (int)g.items.size();
-            a.wh_iters = S->d_work_iters.p + g.off;
+            a.wh_iters = di + g.off;
             a.lds_bytes = g.lds;
             a.nt_max = g.nt_max;
-            e = launch_layout<double>(g.layout, a, g.P, g.wg, gs);
+            e = launch_layout<double>(g.layout, a, g.P, g.wg, s);
         }
         HIPCHK(e);
     }
-    for (int k = 0; k < Store::kGroupStreams; ++k) {
-        if (!used[k]) continue;
-        HIPCHK(hipEventRecord(S->gev[k], S->gs[k]));
-        HIPCHK(hipStreamWaitEvent(s, S->gev[k], 0));
-    }
-    HIPCHK(hipEventRecord(S->ev1, s));
+    HIPCHK(hipEventRecord(S->sev1[slot], s));
     for (const SweepReq* q : reqs)
         HIPCHK(hipMemcpyAsync(q->g_out, S->d_gout.p + q->h->if_base, sizeof(double2) * q->h->n_if,
                               hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(S->h_work_iters, S->d_work_iters.p, sizeof(int) * total,
-                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hi, di, sizeof(int) * total, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+    HIPCHK(hipEventElapsedTime(&ms, S->sev0[slot], S->sev1[slot]));
     std::vector<std::vector<int>> its(reqs.size());
     for (size_t r = 0; r < reqs.size(); ++r) its[r].assign(reqs[r]->h->L, 0);
     for (auto& kv : groups) {
         const Group& g = kv.second;
         for (size_t i = 0; i < g.items.size(); ++i)
-            its[g.items[i].r][g.items[i].l] = S->h_work_iters[g.off + (int64_t)i];
+            its[g.items[i].r][g.items[i].l] = hi[g.off + (int64_t)i];
     }
     for (size_t r = 0; r < reqs.size(); ++r)
         account_sweep(reqs[r]->h, its[r].data(), ms * 1e-3, reqs[r]->prec);
-    S->sched.launches += 1;
     if (ms_out) *ms_out = ms;
     if (groups_out) *groups_out = gi;
     return DD_OK;
-}
-
-void sched_maybe_launch(Store* S, std::unique_lock<std::mutex>& lk) {
-    Sched& Q = S->sched;
-    while (!Q.launching && Q.active > 0 && (int)Q.pending.size() >= Q.active) {
-        std::vector<SweepReq*> batch;
-        batch.swap(Q.pending);
-        Q.launching = true;
-        lk.unlock();
-        const int rc = launch_batch(S, batch);
-        const std::string msg = rc == DD_OK ? std::string() : g_err;
-        lk.lock();
-        for (SweepReq* r : batch) {
-            r->rc = rc;
-            r->done = true;
-        }
-        Q.err = msg;
-        Q.launching = false;
-        Q.cv.notify_all();
-    }
 }
 
 void sched_join(Store* S) {
@@ -714,13 +688,13 @@ void sched_join(Store* S) {
 }
 
 void sched_leave(Store* S) {
-    std::unique_lock<std::mutex> lk(S->sched.mu);
+    std::lock_guard<std::mutex> lk(S->sched.mu);
     S->sched.active -= 1;
-    sched_maybe_launch(S, lk);
 }
 
-// A sweep of a batched handle: post it and wait for the launch that
-// carries it (launched by whichever problem posts last).
+// A sweep of a batched handle: post it; if a launch slot is free, launch
+// everything pending (this sweep included unless another thread already
+// took it), else wait for the launch that carries it.
 int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
                 int prec, double tau, int max_wh) {
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -729,8 +703,33 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
     SweepReq req{h, g_in, g_out, src, with_f, prec, tau, max_wh};
     std::unique_lock<std::mutex> lk(Q.mu);
     Q.pending.push_back(&req);
-    sched_maybe_launch(S, lk);
-    Q.cv.wait(lk, [&] { return req.done; });
+    while (!req.done) {
+        int slot = -1;
+        for (int k = 0; k < Sched::kSlots; ++k)
+            if (!Q.busy[k]) {
+                slot = k;
+                break;
+            }
+        if (slot < 0 || Q.pending.empty()) {
+            Q.cv.wait(lk);
+            continue;
+        }
+        std::vector<SweepReq*> batch;
+        batch.swap(Q.pending);
+        Q.busy[slot] = true;
+        lk.unlock();
+        const int rc = launch_batch(S, batch, slot);
+        const std::string msg = rc == DD_OK ? std::string() : g_err;
+        lk.lock();
+        for (SweepReq* r : batch) {
+            r->rc = rc;
+            r->done = true;
+        }
+        if (rc != DD_OK) Q.err = msg;
+        Q.busy[slot] = false;
+        Q.launches += 1;
+        Q.cv.notify_all();
+    }
     if (req.rc != DD_OK) return fail(req.rc, "batched sweep: %s", Q.err.c_str());
     return DD_OK;
 }
@@ -1352,11 +1351,12 @@ void store_destroy(Store* S) {
     S->d_gin.free(); S->d_gout.free(); S->d_work.free(); S->d_work_iters.free();
     if (S->h_work) (void)hipHostFree(S->h_work);
     if (S->h_work_iters) (void)hipHostFree(S->h_work_iters);
-    for (int i = 0; i < Store::kGroupStreams; ++i) {
-        if (S->gev[i]) (void)hipEventDestroy(S->gev[i]);
-        if (S->gs[i]) (void)hipStreamDestroy(S->gs[i]);
+    for (int i = 0; i < Sched::kSlots; ++i) {
+        if (S->ss[i]) (void)hipStreamSynchronize(S->ss[i]);
+        if (S->sev0[i]) (void)hipEventDestroy(S->sev0[i]);
+        if (S->sev1[i]) (void)hipEventDestroy(S->sev1[i]);
+        if (S->ss[i]) (void)hipStreamDestroy(S->ss[i]);
     }
-    if (S->ev_in) (void)hipEventDestroy(S->ev_in);
     if (S->ev0) (void)hipEventDestroy(S->ev0);
     if (S->ev1) (void)hipEventDestroy(S->ev1);
     if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -1432,16 +1432,17 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
     if (shared) {
         STCHK(S->d_gin.alloc(ci));
         STCHK(S->d_gout.alloc(ci));
-        STCHK(S->d_work.alloc(cit));
-        STCHK(S->d_work_iters.alloc(cit));
-        STCHK(hipHostMalloc((void**)&S->h_work, sizeof(wdd::SubDesc) * std::max<int64_t>(cit, 1)));
-        STCHK(hipHostMalloc((void**)&S->h_work_iters, sizeof(int) * std::max<int64_t>(cit, 1)));
-        STCHK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
-        for (int i = 0; i < Store::kGroupStreams; ++i) {
-            STCHK(hipStreamCreateWithFlags(&S->gs[i], hipStreamNonBlocking));
-            STCHK(hipEventCreateWithFlags(&S->gev[i], hipEventDisableTiming));
+        const int64_t nw = Sched::kSlots * std::max<int64_t>(cit, 1);
+        STCHK(S->d_work.alloc(nw));
+        STCHK(S->d_work_iters.alloc(nw));
+        STCHK(hipHostMalloc((void**)&S->h_work, sizeof(wdd::SubDesc) * nw));
+        STCHK(hipHostMalloc((void**)&S->h_work_iters, sizeof(int) * nw));
+        for (int i = 0; i < Sched::kSlots; ++i) {
+            STCHK(hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking));
+            STCHK(hipEventCreate(&S->sev0[i]));
+            STCHK(hipEventCreate(&S->sev1[i]));
         }
-        bytes += ci * 32 + cit * (sizeof(wdd::SubDesc) + 4);
+        bytes += ci * 32 + nw * (sizeof(wdd::SubDesc) + 4);
     }
 #undef STCHK
     S->bytes = bytes;
@@ -2009,6 +2010,18 @@ struct dd_batch {
     Store* store = nullptr;
     std::vector<dd_handle*> probs;
     int64_t launches = 0;
+    std::mutex mu;               // progress of a running solve
+    std::condition_variable cv;
+    int finished = 0;
+    bool running = false;
+    // state of a running solve (between dd_batch_solve_start and _finish)
+    std::vector<std::thread> th;
+    std::vector<int> rc;
+    std::vector<std::string> msg;
+    std::vector<dd_stats> sts;
+    dd_stats* st_out = nullptr;
+    int* rc_out = nullptr;
+    int64_t l0 = 0;
 };
 
 namespace {
@@ -2048,7 +2061,14 @@ void batch_free(dd_batch* b) {
 extern "C" {
 
 void dd_batch_destroy(dd_batch* b) {
-    if (b) batch_free(b);
+    if (!b) return;
+    bool running;
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        running = b->running;
+    }
+    if (running) (void)dd_batch_solve_finish(b);
+    batch_free(b);
 }
 
 int dd_batch_setup(dd_batch** out, int n, const dd_problem* probs, const dd_options* opt) {
@@ -2111,50 +2131,97 @@ int dd_batch_handle(dd_batch* b, int i, dd_handle** h) {
     return DD_OK;
 }
 
-int dd_batch_solve(dd_batch* b, const double* const* f_re, const double* const* f_im, double tol,
-                   int max_iter, double* const* u_re, double* const* u_im, dd_stats* st, int* rcs) {
+int dd_batch_solve_start(dd_batch* b, const double* const* f_re, const double* const* f_im,
+                         double tol, int max_iter, double* const* u_re, double* const* u_im,
+                         dd_stats* st, int* rcs) {
     if (!b) return fail(DD_EINVAL, "null batch");
     if (!u_re || !u_im) return fail(DD_EINVAL, "null output arrays");
     if (!(tol >= 0.0) || max_iter < 1) return fail(DD_EINVAL, "tol must be >= 0 and max_iter >= 1");
     const int n = (int)b->probs.size();
     for (int i = 0; i < n; ++i)
         if (!u_re[i] || !u_im[i]) return fail(DD_EINVAL, "null output for problem %d", i);
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        if (b->running) return fail(DD_EINVAL, "a batch solve is already running");
+        b->finished = 0;
+        b->running = true;
+    }
     Store* S = b->store;
-    const int64_t l0 = S->sched.launches;
-    std::vector<int> rc(n, DD_OK);
-    std::vector<std::string> msg(n);
-    std::vector<dd_stats> sts(n);
-    // every problem joins before any posts, so the first rendezvous waits
-    // for all of them
+    b->l0 = S->sched.launches;
+    b->rc.assign(n, DD_OK);
+    b->msg.assign(n, std::string());
+    b->sts.assign(n, dd_stats{});
+    b->st_out = st;
+    b->rc_out = rcs;
     for (dd_handle* h : b->probs) {
         h->batched = true;
         sched_join(S);
     }
-    std::vector<std::thread> th;
-    th.reserve(n);
+    b->th.clear();
+    b->th.reserve(n);
     for (int i = 0; i < n; ++i) {
-        th.emplace_back([&, i]() {
+        const double* fr = f_re ? f_re[i] : nullptr;
+        const double* fi = f_im ? f_im[i] : nullptr;
+        double* ur = u_re[i];
+        double* ui = u_im[i];
+        b->th.emplace_back([b, S, i, fr, fi, tol, max_iter, ur, ui]() {
             (void)hipSetDevice(S->dev);
-            rc[i] = dd_solve(b->probs[i], f_re ? f_re[i] : nullptr, f_im ? f_im[i] : nullptr,
-                             nullptr, nullptr, tol, max_iter, u_re[i], u_im[i], &sts[i]);
-            msg[i] = g_err;
+            b->rc[i] = dd_solve(b->probs[i], fr, fi, nullptr, nullptr, tol, max_iter, ur, ui,
+                                &b->sts[i]);
+            b->msg[i] = g_err;
             sched_leave(S);
+            std::lock_guard<std::mutex> lk(b->mu);
+            b->finished += 1;
+            b->cv.notify_all();
         });
     }
-    for (auto& t : th) t.join();
+    return DD_OK;
+}
+
+int dd_batch_solve_finish(dd_batch* b) {
+    if (!b) return fail(DD_EINVAL, "null batch");
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        if (!b->running) return fail(DD_EINVAL, "no batch solve is running");
+    }
+    for (auto& t : b->th) t.join();
+    b->th.clear();
+    Store* S = b->store;
     for (dd_handle* h : b->probs) h->batched = false;
-    b->launches = S->sched.launches - l0;
-    if (st) std::copy(sts.begin(), sts.end(), st);
-    if (rcs) std::copy(rc.begin(), rc.end(), rcs);
+    b->launches = S->sched.launches - b->l0;
+    const int n = (int)b->probs.size();
+    if (b->st_out) std::copy(b->sts.begin(), b->sts.end(), b->st_out);
+    if (b->rc_out) std::copy(b->rc.begin(), b->rc.end(), b->rc_out);
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->running = false;
+        b->cv.notify_all();
+    }
     int worst = DD_OK;
     for (int i = 0; i < n; ++i) {
-        if (rc[i] != DD_OK && rc[i] != DD_ENOTCONV) return fail(rc[i], "problem %d: %s", i, msg[i].c_str());
-        if (rc[i] == DD_ENOTCONV && worst == DD_OK) {
+        if (b->rc[i] != DD_OK && b->rc[i] != DD_ENOTCONV)
+            return fail(b->rc[i], "problem %d: %s", i, b->msg[i].c_str());
+        if (b->rc[i] == DD_ENOTCONV && worst == DD_OK) {
             worst = DD_ENOTCONV;
-            fail(DD_ENOTCONV, "problem %d: %s", i, msg[i].c_str());
+            fail(DD_ENOTCONV, "problem %d: %s", i, b->msg[i].c_str());
         }
     }
     return worst;
+}
+
+int dd_batch_solve(dd_batch* b, const double* const* f_re, const double* const* f_im, double tol,
+                   int max_iter, double* const* u_re, double* const* u_im, dd_stats* st, int* rcs) {
+    CHK(dd_batch_solve_start(b, f_re, f_im, tol, max_iter, u_re, u_im, st, rcs));
+    return dd_batch_solve_finish(b);
+}
+
+int dd_batch_wait_progress(dd_batch* b, int seen, int* finished) {
+    if (!b || !finished) return fail(DD_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(b->mu);
+    b->cv.wait(lk, [&] { return b->finished > seen || !b->running ||
+                             b->finished >= (int)b->probs.size(); });
+    *finished = b->finished;
+    return DD_OK;
 }
 
 int dd_batch_launches(const dd_batch* b, int64_t* launches) {
@@ -2177,13 +2244,13 @@ int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, doub
     }
     std::vector<SweepReq*> rp;
     for (auto& r : reqs) rp.push_back(&r);
-    CHK(launch_batch(S, rp));
+    CHK(launch_batch(S, rp, 0));
     for (dd_handle* h : b->probs) reset_stats(h);
     double total_ms = 0.0;
     int groups = 0;
     for (int r = 0; r < reps; ++r) {
         double m = 0.0;
-        CHK(launch_batch(S, rp, &m, &groups));
+        CHK(launch_batch(S, rp, 0, &m, &groups));
         total_ms += m;
     }
     *ms = total_ms / reps;
@@ -2217,6 +2284,7 @@ struct Request {
     dd_stats st{};
     double t_submit = 0.0, t_start = 0.0, t_done = 0.0;
     size_t bytes = 0;
+    bool claimed = false;   // returned by dd_engine_wait_any
 };
 
 }  // namespace
@@ -2437,6 +2505,24 @@ int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stat
     delete r;
     if (rc != DD_OK) g_err = msg;
     return rc;
+}
+
+int dd_engine_wait_any(dd_engine* e, int64_t* id) {
+    if (!e || !id) return fail(DD_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(e->mu);
+    if (e->reqs.empty()) return fail(DD_EINVAL, "no outstanding request");
+    int64_t found = -1;
+    e->cv.wait(lk, [&] {
+        for (auto& kv : e->reqs)
+            if (kv.second->state == DD_REQ_DONE && !kv.second->claimed) {
+                found = kv.first;
+                return true;
+            }
+        return false;
+    });
+    e->reqs[found]->claimed = true;
+    *id = found;
+    return DD_OK;
 }
 
 int dd_engine_get_info(dd_engine* e, dd_engine_info* info) {

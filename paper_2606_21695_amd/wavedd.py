@@ -27,9 +27,10 @@ EXPORTS = [
     "dd_apply_stiffness", "dd_residual", "dd_apply_operator_device", "dd_get_state",
     "dd_set_state", "dd_time_sweep", "dd_layout", "dd_mesh_coords",
     "dd_batch_setup", "dd_batch_destroy", "dd_batch_handle", "dd_batch_solve",
-    "dd_batch_time_sweep", "dd_batch_launches",
+    "dd_batch_time_sweep", "dd_batch_launches", "dd_batch_wait_progress",
+    "dd_batch_solve_start", "dd_batch_solve_finish",
     "dd_engine_create", "dd_engine_destroy", "dd_engine_submit", "dd_engine_status",
-    "dd_engine_wait", "dd_engine_get_info",
+    "dd_engine_wait", "dd_engine_get_info", "dd_engine_wait_any",
 ]
 DD_REQ_QUEUED, DD_REQ_RUNNING, DD_REQ_DONE = 0, 1, 2
 
@@ -146,6 +147,11 @@ def load():
                             C.POINTER(D), C.POINTER(dd_stats), C.POINTER(C.c_int)], C.c_int),
         "dd_batch_time_sweep": ([P, C.c_int, C.c_int, D, D, C.POINTER(C.c_int)], C.c_int),
         "dd_batch_launches": ([P, I64], C.c_int),
+        "dd_batch_wait_progress": ([P, C.c_int, C.POINTER(C.c_int)], C.c_int),
+        "dd_batch_solve_start": ([P, C.POINTER(D), C.POINTER(D), C.c_double, C.c_int,
+                                  C.POINTER(D), C.POINTER(D), C.POINTER(dd_stats),
+                                  C.POINTER(C.c_int)], C.c_int),
+        "dd_batch_solve_finish": ([P], C.c_int),
         "dd_engine_create": ([C.POINTER(P), C.c_size_t, C.c_int, C.POINTER(dd_options)],
                              C.c_int),
         "dd_engine_destroy": ([P], None),
@@ -154,6 +160,7 @@ def load():
         "dd_engine_status": ([P, C.c_int64, C.POINTER(C.c_int)], C.c_int),
         "dd_engine_wait": ([P, C.c_int64, D, D, C.POINTER(dd_stats), D], C.c_int),
         "dd_engine_get_info": ([P, C.POINTER(dd_engine_info)], C.c_int),
+        "dd_engine_wait_any": ([P, I64], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -395,10 +402,11 @@ def dd_batch_handle(b, i):
     return h
 
 
-def dd_batch_solve(b, fs, tol=1e-8, max_iter=1000, allow_notconv=False):
+def dd_batch_solve(b, fs, tol=1e-8, max_iter=1000, allow_notconv=False, progress=None):
     """Solve every problem of the batch; fs: list of real nodal sources (or
-    None).  Returns (list of complex u, list of stats dicts, per-problem
-    codes, overall code)."""
+    None).  progress(k): called each time the k-th problem finishes.
+    Returns (list of complex u, list of stats dicts, per-problem codes,
+    overall code)."""
     n = len(fs)
     sizes = [dd_sizes(dd_batch_handle(b, i))["n_global"] for i in range(n)]
     keep = [None if f is None else _f64(f) for f in fs]
@@ -410,7 +418,14 @@ def dd_batch_solve(b, fs, tol=1e-8, max_iter=1000, allow_notconv=False):
     u_im = (PD * n)(*[_dp(u) for u in uim])
     st = (dd_stats * n)()
     rcs = (C.c_int * n)()
-    rc = load().dd_batch_solve(b, f_re, None, tol, max_iter, u_re, u_im, st, rcs)
+    lib = load()
+    _check(lib.dd_batch_solve_start(b, f_re, None, tol, max_iter, u_re, u_im, st, rcs))
+    done = 0
+    if progress is not None:
+        while done < n:
+            done = dd_batch_wait_progress(b, done)
+            progress(done)
+    rc = lib.dd_batch_solve_finish(b)
     _check(rc, (DD_ENOTCONV,) if allow_notconv else ())
     return ([ure[i] + 1j * uim[i] for i in range(n)], [st[i].as_dict() for i in range(n)],
             list(rcs), rc)
@@ -421,6 +436,14 @@ def dd_batch_time_sweep(b, reps=5, fixed_iters=5):
     _check(load().dd_batch_time_sweep(b, reps, fixed_iters, C.byref(ms), C.byref(du),
                                       C.byref(nl)))
     return ms.value, du.value, nl.value
+
+
+def dd_batch_wait_progress(b, seen):
+    """Block until more than `seen` problems of a running dd_batch_solve have
+    finished; returns the count."""
+    v = C.c_int()
+    _check(load().dd_batch_wait_progress(b, seen, C.byref(v)))
+    return v.value
 
 
 def dd_batch_launches(b):
@@ -463,6 +486,13 @@ def dd_engine_wait(e, rid, n_global, allow_notconv=False):
     rc = load().dd_engine_wait(e, rid, _dp(ure), _dp(uim), C.byref(st), _dp(t))
     _check(rc, (DD_ENOTCONV,) if allow_notconv else ())
     return ure + 1j * uim, st.as_dict(), tuple(t), rc
+
+
+def dd_engine_wait_any(e):
+    """Id of some finished, not yet collected request (blocks)."""
+    rid = C.c_int64()
+    _check(load().dd_engine_wait_any(e, C.byref(rid)))
+    return rid.value
 
 
 def dd_engine_get_info(e):

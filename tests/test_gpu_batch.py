@@ -65,8 +65,9 @@ def test_batch_matches_single_solves(gpu_lib):
     finally:
         W.dd_batch_destroy(b)
     assert rc == W.DD_OK and all(r == W.DD_OK for r in rcs)
-    # one launch round per sweep of the problem with the most sweeps
-    assert launches == max(st["sweeps"] for st in sts)
+    # a launch carries at most one sweep of each problem and may carry several
+    # problems' sweeps
+    assert max(st["sweeps"] for st in sts) <= launches <= sum(st["sweeps"] for st in sts)
     for i, s in enumerate(specs):
         u1, st1 = _single(W, s, 1e-8, tau_in=1e-12, layout=lays[i])
         print(f"problem {i}: batch iters {sts[i]['outer_iters']} single {st1['outer_iters']}",

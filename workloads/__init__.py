@@ -150,7 +150,7 @@ def c2_small(seed=2):
 def c3(seed=2):
     om = _omega_ppw(3, 1.0 / 256, 1.0 / 3.0, 10.0)
     return Workload("c3", 512, 512, 3, 8, 8, om, y_waveguide(seed),
-                    gaussian(0.51, 0.15, 0.01), tol=1e-8, tau_in=1e-7)
+                    gaussian(0.51, 0.15, 0.01), tol=1e-8, tau_in=1e-12)
 
 
 def c4(seed=4, total=400):
@@ -172,7 +172,7 @@ def c4(seed=4, total=400):
         sxp, syp = ox + rng.uniform(0.2, 0.8) * W, oy + rng.uniform(0.2, 0.8) * H
         probs.append(Workload(f"c4_{len(probs)}", gx * s, gy * s, P, gx, gy, omega, c,
                               gaussian(sxp, syp, 3 * h), ox, ox + W, oy, oy + H,
-                              tol=1e-6, tau_in=1e-7))
+                              tol=1e-6, tau_in=1e-5))
         count += gx * gy
     return probs
 
@@ -213,7 +213,7 @@ def c5(seed=5, n_requests=2000):
         def f_fn(X, Y, srcs=srcs):
             return sum(s_(X, Y) for s_ in srcs)
         reqs.append(Workload(f"c5_{r}", n, n, P, g, g, omega, c_fn, f_fn, tol=1e-6,
-                             tau_in=1e-7))
+                             tau_in=1e-5))
     return reqs
 
 
