@@ -293,6 +293,66 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def protocol_bench(args):
+    """The paper's DD-cycle timing (Sec. VII-A): sweeps of exactly 5
+    WaveHoltz iterations per subdomain from random complex interface data,
+    sources off, averaged over --steps launches after --warmup."""
+    import torch
+    import workloads
+    from paper_2606_21695_amd import wavedd as W
+    W.require_gpu()
+    torch.cuda.set_device(0)
+    prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
+    if args.config == "c4":
+        wls = workloads.c4()
+        b = W.dd_batch_setup([W.workload_spec(wl) for wl in wls],
+                             W.dd_default_options(precision=prec))
+        rng = np.random.default_rng(4)
+        for i in range(len(wls)):
+            h = W.dd_batch_handle(b, i)
+            n = W.dd_sizes(h)["n_iface"]
+            W.dd_set_state(h, rng.standard_normal(n) + 1j * rng.standard_normal(n))
+        ms, dof, nl = W.dd_batch_time_sweep(b, reps=args.steps, fixed_iters=5)
+        W.dd_batch_destroy(b)
+        layout, kernel = "per problem (autotuned per shape)", f"{nl} batched launches per round"
+        desc = f"c4: {len(wls)} problems, {sum(wl.sx * wl.sy for wl in wls)} subdomains"
+        P_for_flops = None
+        flop = None
+    else:
+        wl = workloads.CONFIGS[args.config]()
+        prob = W.Problem(wl, precision=prec, tau_in=0.0, max_wh=5)
+        h = prob.h
+        rng = np.random.default_rng(1)
+        n = W.dd_sizes(h)["n_iface"]
+        W.dd_set_state(h, rng.standard_normal(n) + 1j * rng.standard_normal(n))
+        ms, dof = W.dd_time_sweep(h, args.steps, 5)
+        lay, wg = W.dd_layout(h)
+        prob.close()
+        layout = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay]
+        kernel = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
+                  4: "sweep_stream_kernel"}[lay]
+        desc = (f"{args.config}: {wl.nx}x{wl.ny} elements P={wl.P}, {wl.sx}x{wl.sy} subdomains, "
+                f"omega={wl.omega:.2f}")
+        flop = flops_per_update(wl.P) * dof
+    out = {"metric": "WaveHoltz DOF-updates/s (DD cycle, 5 WaveHoltz iterations, random input)",
+           "value": dof / (ms * 1e-3), "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision.replace("fp", "f"),
+           "data": "synthetic (random complex interface data)",
+           "config": {"workload": desc, "layout": layout, "kernel": kernel},
+           "dof_updates_per_launch": dof}
+    if flop is not None:
+        peak = PEAK_TFLOPS[args.precision]
+        ach = flop / (ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                           "frac": ach / peak, "traffic": None}
+        if layout == "stream":
+            gbs = BYTES_STREAM[args.precision] * dof / (ms * 1e-3) / 1e9
+            out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                               "frac": gbs / 8000.0, "traffic": None, "alu_tflops": ach}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,9 +367,13 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
     ap.add_argument("--serve", action="store_true", help="serving engine on the c5 stream")
-    ap.add_argument("--max-wh", type=int, default=1000,
-                    help="WaveHoltz cap per subdomain solve for the batch / serving modes "
-                         "(large subdomains need hundreds of periods)")
+    ap.add_argument("--max-wh", type=int, default=None,
+                    help="WaveHoltz cap per subdomain solve (default: the library's 100 for "
+                         "the 256x256 workloads, 1000 for the 512x512, batch and serving "
+                         "workloads, whose large subdomains need hundreds of periods)")
+    ap.add_argument("--protocol", action="store_true",
+                    help="the paper's DD-cycle timing instead of solves: sweeps of exactly 5 "
+                         "WaveHoltz iterations per subdomain on random interface data")
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-nodes", type=int, default=600000,
                     help="serving mode: skip requests with more global nodes")
@@ -326,8 +390,20 @@ def main():
                                    "path is built; use --gpus 1"}))
         sys.exit(2)
 
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.ones_like(a)
+        torch.cuda.synchronize()
+        a.copy_(b)
+        torch.cuda.synchronize()
+        del a, b
+    if args.max_wh is None:
+        args.max_wh = 100 if args.config in ("c1", "c2", "c2_small") and not args.serve else 1000
     if args.serve:
         return serve_bench(args)
+    if args.protocol:
+        return protocol_bench(args)
     if args.config == "c4":
         return batch_bench(args)
     import torch
@@ -336,20 +412,13 @@ def main():
 
     W.require_gpu()
     torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        b = torch.ones_like(a)
-        torch.cuda.synchronize()
-        a.copy_(b)
-        torch.cuda.synchronize()
-        del a, b
     wl = workloads.CONFIGS[args.config]()
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
     tau = wl.tau_in if prec == W.DD_FP64 else max(wl.tau_in, 1e-6)
     if args.tau_in is not None:
         tau = args.tau_in
     t0 = time.perf_counter()
-    prob = W.Problem(wl, precision=prec, tau_in=tau, relax=args.relax)
+    prob = W.Problem(wl, precision=prec, tau_in=tau, relax=args.relax, max_wh=args.max_wh)
     setup_s = time.perf_counter() - t0
     h = prob.h
     sizes = W.dd_sizes(h)
@@ -414,7 +483,7 @@ def main():
                                f"{wl.sx}x{wl.sy} subdomains, omega={wl.omega:.2f}, tol={wl.tol}",
                    "precision": args.precision,
                    "layout": {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay],
-                   "wg_threads": wg, "tau_in": tau, "relax": args.relax},
+                   "wg_threads": wg, "tau_in": tau, "relax": args.relax, "max_wh": args.max_wh},
         "solves_per_s": args.steps / total,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},

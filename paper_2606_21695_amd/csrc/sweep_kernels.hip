@@ -1389,10 +1389,10 @@ struct StreamGeom {
 template <typename Real>
 constexpr int stream_ahead() { return sizeof(Real) == 8 ? 2 : 3; }
 
-// Node record of the STREAM workspace (kStreamRec Reals per node): the
-// state quad {pd, vr, vi, alpha} and the coefficient quad {betaX, betaY,
-// beta Re b, beta Im b}.  A step reads both quads and writes the state quad.
-constexpr int kStreamRec = kStreamRecord;
+// STREAM workspace per node: the state quad {pd, vr, vi, alpha} in one
+// plane and the coefficient quad {betaX, betaY, beta Re b, beta Im b} in a
+// second (so the cache lines a step writes hold state only).  A step reads
+// both quads and writes the state quad.
 template <typename Real>
 struct alignas(4 * sizeof(Real)) Quad {
     Real a, b, c, d;
@@ -1412,14 +1412,14 @@ struct StreamRow {
 template <typename Real, int P>
 __device__ __forceinline__ void stream_fetch(StreamRow<Real>& r, const StreamGeom<Real, P>& G,
                                              const Real* cur, int stride, int j, int nxl,
-                                             const Real* NS) {
+                                             const Real* NSt, const Real* NCf) {
     const bool inrow = j < G.j1;
     const int jc = inrow ? j : G.j1 - 1;
     const Real pn = cur[(jc + P + kMaxP) * stride + G.pcol];
     r.pn = (G.colv && inrow) ? pn : Real(0);
-    const Real* rec = NS + (size_t)kStreamRec * (jc * nxl + G.ic);
-    r.st = *reinterpret_cast<const Quad<Real>*>(rec);
-    r.cf = *reinterpret_cast<const Quad<Real>*>(rec + 4);
+    const size_t n = (size_t)(jc * nxl + G.ic);
+    r.st = *reinterpret_cast<const Quad<Real>*>(NSt + 4 * n);
+    r.cf = *reinterpret_cast<const Quad<Real>*>(NCf + 4 * n);
 }
 
 // One step of the STREAM layout for the column segment of this lane: walk
@@ -1430,7 +1430,8 @@ __device__ __forceinline__ void stream_fetch(StreamRow<Real>& r, const StreamGeo
 // writes u = (2/N_t) v and accumulates the fixed-point residual instead.
 template <typename Real, int P, bool LAST>
 __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const Real* cur, Real* nxt,
-                                            int stride, int nxl, int nyl, Real* NS, const Real* WT,
+                                            int stride, int nxl, int nyl, Real* NSt, const Real* NCf,
+                                            const Real* WT,
                                             const Quad<Real> tb, Real sig, const SweepArgs<Real>& A,
                                             const SubDesc& d, bool has_old, double& dsum,
                                             double& nsum) {
@@ -1445,13 +1446,13 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
     }
     StreamRow<Real> R[kAhead];
 #pragma unroll
-    for (int q = 0; q < kAhead; ++q) stream_fetch(R[q], G, cur, stride, G.j0 + q, nxl, NS);
+    for (int q = 0; q < kAhead; ++q) stream_fetch(R[q], G, cur, stride, G.j0 + q, nxl, NSt, NCf);
     for (int jb = G.j0; jb < G.j1; jb += kAhead) {
 #pragma unroll
         for (int q = 0; q < kAhead; ++q) {
             const int j = jb + q;
             const StreamRow<Real> r = R[q];
-            stream_fetch(R[q], G, cur, stride, j + kAhead, nxl, NS);
+            stream_fetch(R[q], G, cur, stride, j + kAhead, nxl, NSt, NCf);
 #pragma unroll
             for (int k = 0; k < 2 * P; ++k) win[k] = win[k + 1];
             win[2 * P] = r.pn;
@@ -1475,7 +1476,7 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
             const int n = j * nxl + G.i;
             if (!LAST) {
                 if (put) {
-                    *reinterpret_cast<Quad<Real>*>(NS + (size_t)kStreamRec * n) =
+                    *reinterpret_cast<Quad<Real>*>(NSt + 4 * (size_t)n) =
                         Quad<Real>{pd, vr, vi, r.st.d};
                     nxt[(j + kMaxP) * stride + G.pcol] = fma(sig, pd, p);
                 }
@@ -1510,7 +1511,8 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const Real* TAB = lds + kStreamTab;
     Real* p0 = A.ws_p + d.ws_off;
     Real* p1 = p0 + stream_pad_nodes(nxl, nyl);
-    Real* NS = A.ws_s + (size_t)kStreamRec * d.node_off;
+    Real* NSt = A.ws_s + 4 * (size_t)d.node_off;
+    Real* NCf = A.ws_s + 4 * ((size_t)A.ws_stride + d.node_off);
     const Real* AL = A.coef.alpha + d.node_off;
     // beta * b (eq. (4) right-hand side with the interface data)
     {
@@ -1518,8 +1520,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
         for (int n = tid; n < nloc; n += bd) {
             const double be = (double)A.coef.beta[d.node_off + n];
             const double2 b = assemble_b(A, d, il, jl);
-            Real* rec = NS + (size_t)kStreamRec * n;
-            *reinterpret_cast<Quad<Real>*>(rec + 4) =
+            *reinterpret_cast<Quad<Real>*>(NCf + 4 * (size_t)n) =
                 Quad<Real>{A.coef.betaX[d.node_off + n], A.coef.betaY[d.node_off + n],
                            (Real)(be * b.x), (Real)(be * b.y)};
             il += di;
@@ -1547,7 +1548,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
                     p = (Real)u.x;
                     pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
                 }
-                *reinterpret_cast<Quad<Real>*>(NS + (size_t)kStreamRec * n) =
+                *reinterpret_cast<Quad<Real>*>(NSt + 4 * (size_t)n) =
                     Quad<Real>{pd, k0 * p, kh0 * pd, AL[n]};
                 p1[(jl + kMaxP) * stride + il + kMaxP] = fma(sig, pd, p);
                 il += di;
@@ -1563,11 +1564,11 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             if (!G.active) continue;
             const Quad<Real> tb{TAB[4 * nu + 0], TAB[4 * nu + 1], TAB[4 * nu + 2], TAB[4 * nu + 3]};
             if (nu < nt - 1)
-                stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, NS, WT, tb, sig, A, d,
-                                            m > 0, dsum, nsum);
+                stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
+                                            A, d, m > 0, dsum, nsum);
             else
-                stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, NS, WT, tb, sig, A, d,
-                                           m > 0, dsum, nsum);
+                stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
+                                           A, d, m > 0, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
         it = m + 1;

@@ -62,7 +62,7 @@ struct SweepArgs {
     double tau;              // inner tolerance (<= 0: fixed count)
     int max_wh;              // iteration cap / fixed count
     Real* ws_p;              // STREAM layout: padded p grids (2 per subdomain, at desc.ws_off)
-    Real* ws_s;              // STREAM layout: kStreamRecord Reals per node (node-indexed)
+    Real* ws_s;              // STREAM layout: 4 Reals per node of state, then 4 of coefficients
     int64_t ws_stride;       // node capacity of ws_s
     size_t lds_bytes;        // dynamic LDS per workgroup of the launch
     int nt_max;              // largest N_t of the launch (sizes the LDS tables)
