@@ -28,17 +28,31 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
-# a 256 MiB copy: fetch x2.000, write x1.000), keyed by the kernel source hash
-# and (config, precision, layout); reported as null once the kernel changes.
+# a 256 MiB copy: fetch x2.000, write x1.000), keyed by the hash of the
+# kernel's source (its layout section plus the shared helpers) and the run;
+# reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    ("7680b45e72439716", "c2", "fp64", 3): 43044 * 1024,
+    ("e901ef5d2ff97435", "solve", "c2", "fp64"): round((15289.7 * 2.0 + 15423.7) * 1024),
+    ("dde7fb3e43b347ad", "protocol", "c3", "fp64"): round((57468974.2 * 2.0 + 63327348.4) * 1024),
+    ("dde7fb3e43b347ad", "protocol", "c3", "fp32"): round((28801302.8 * 2.0 + 31880181.1) * 1024),
 }
 
+# section markers of each layout in the kernel source
+_SECTIONS = {1: ("// NODE layout (one DOF per thread)", "// STREAM layout"),
+             2: ("// PATCH layout, one barrier per step", "// NODE layout (one DOF per thread)"),
+             3: ("// PATCH layout\n", "// PATCH layout, one barrier per step"),
+             4: ("// STREAM layout", "}  // namespace\n")}
 
-def kernel_hash():
+
+def kernel_hash(layout):
+    """Hash of the shared device helpers plus the given layout's section."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    src = open(os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep_kernels.hip")).read()
+    head = src[:src.index("// PATCH layout\n")]
+    a, b = _SECTIONS[layout]
+    i = src.index(a)
+    body = src[i:src.index(b, i + len(a))]
+    return hashlib.sha256((head + body).encode()).hexdigest()[:16]
 
 
 def log(msg):
@@ -316,8 +330,8 @@ def protocol_bench(args):
         W.dd_batch_destroy(b)
         layout, kernel = "per problem (autotuned per shape)", f"{nl} batched launches per round"
         desc = f"c4: {len(wls)} problems, {sum(wl.sx * wl.sy for wl in wls)} subdomains"
-        P_for_flops = None
         flop = None
+        traffic = None
     else:
         wl = workloads.CONFIGS[args.config]()
         prob = W.Problem(wl, precision=prec, tau_in=0.0, max_wh=5)
@@ -327,6 +341,7 @@ def protocol_bench(args):
         W.dd_set_state(h, rng.standard_normal(n) + 1j * rng.standard_normal(n))
         ms, dof = W.dd_time_sweep(h, args.steps, 5)
         lay, wg = W.dd_layout(h)
+        traffic = MEASURED_TRAFFIC.get((kernel_hash(lay), "protocol", args.config, args.precision))
         prob.close()
         layout = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay]
         kernel = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
@@ -345,11 +360,12 @@ def protocol_bench(args):
         peak = PEAK_TFLOPS[args.precision]
         ach = flop / (ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                           "frac": ach / peak, "traffic": None}
+                           "frac": ach / peak, "traffic": traffic, "kernel": kernel}
         if layout == "stream":
             gbs = BYTES_STREAM[args.precision] * dof / (ms * 1e-3) / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
-                               "frac": gbs / 8000.0, "traffic": None, "alu_tflops": ach}
+                               "frac": gbs / 8000.0, "traffic": traffic, "alu_tflops": ach,
+                               "kernel": kernel, "byte_per_dof_update": BYTES_STREAM[args.precision]}
     print(json.dumps(out))
 
 
@@ -496,7 +512,8 @@ def main():
         "true_rel_residual_interface": stats[-1]["true_rel_residual"],
         "setup_s": setup_s,
         "roofline": dict(roof, **{
-            "traffic": MEASURED_TRAFFIC.get((kernel_hash(), args.config, args.precision, lay)),
+            "traffic": MEASURED_TRAFFIC.get((kernel_hash(lay), "solve", args.config,
+                                             args.precision)),
             "kernel": {1: "sweep_node_kernel", 2: "sweep_patch1_kernel",
                        3: "sweep_patch_kernel", 4: "sweep_stream_kernel"}[lay],
             "flop_per_dof_update": fl,
