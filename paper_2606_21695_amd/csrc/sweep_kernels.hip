@@ -1387,7 +1387,7 @@ struct StreamGeom {
 // many rows ahead of their use, so each wave has several rows of memory
 // traffic outstanding).
 template <typename Real>
-constexpr int stream_ahead() { return sizeof(Real) == 8 ? 2 : 3; }
+constexpr int stream_ahead() { return sizeof(Real) == 8 ? 2 : 4; }
 
 // STREAM workspace per node: the state quad {pd, vr, vi, alpha} in one
 // plane and the coefficient quad {betaX, betaY, beta Re b, beta Im b} in a
