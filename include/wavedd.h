@@ -105,6 +105,13 @@ typedef struct {
                         k-th GMRES matvec uses tau = clamp(relax * tol / r_k, tau_in, 1e-2),
                         r_k the current relative outer residual; the true residual at
                         exit is computed with tau_in.  0 = fixed tau_in (default). */
+    int warm;        /* 1: warm start (Sec. V: WaveHoltz may start from any u; the paper
+                        names a previous iterate as the better start).  Applies to the
+                        fixed-point outer iteration (outer = DD_OUTER_FIXED), whose sweeps
+                        then take G + g_phys with sources on and start WaveHoltz from the
+                        previous sweep's subdomain solutions.  Krylov matvec inputs are
+                        unrelated from one matvec to the next, so GMRES ignores it.
+                        0 = every WaveHoltz solve starts from u = 0 (default). */
 } dd_options;
 
 typedef struct {
@@ -123,7 +130,7 @@ typedef struct {
 } dd_stats;
 
 /* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
- * no N_t override, cfl 0.9, refine 4, relax 0. */
+ * no N_t override, cfl 0.9, refine 4, relax 0, warm 0. */
 int dd_default_options(dd_options* opt);
 
 /* Set up a problem (Sec. II-IV): mesh, degree P in [1, 4], wavespeed c > 0

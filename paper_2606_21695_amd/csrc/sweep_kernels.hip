@@ -479,13 +479,15 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
     int it = 0;
     const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    // warm start: the first WaveHoltz iteration starts from the current u
+    const bool warm = A.warm != 0 || (d.flags & 1) != 0;
     for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                if (m > 0 && C.hasP) {
+                if ((m > 0 || warm) && C.hasP) {
                     const double2 u = A.u[base + (int64_t)b * nxl + a];
                     p[a][b] = (Real)u.x;
                     pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
@@ -496,7 +498,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
                 vr[a][b] = k0 * p[a][b];
                 vi[a][b] = kh0 * pd[a][b];
             }
-        if (C.hasE) slot_init(e, A, d, m > 0, k0, kh0);
+        if (C.hasE) slot_init(e, A, d, m > 0 || warm, k0, kh0);
 
         for (int nu = 1; nu < nt; ++nu) {
             const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
@@ -630,7 +632,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
                     const double ur = d.two_over_nt * (double)vr[a][b];
                     const double ui = d.two_over_nt * (double)vi[a][b];
                     double orr = 0.0, oi = 0.0;
-                    if (m > 0) {
+                    if (m > 0 || warm) {
                         const double2 o = A.u[n];
                         orr = o.x;
                         oi = o.y;
@@ -640,7 +642,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
                     A.u[n] = make_double2(ur, ui);
                 }
         }
-        if (C.hasE) slot_finish(e, A, d, m > 0, dsum, nsum);
+        if (C.hasE) slot_finish(e, A, d, m > 0 || warm, dsum, nsum);
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;  // non-finite iterate: stop, reported by the host
@@ -913,13 +915,15 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
     int it = 0;
     const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    // warm start: the first WaveHoltz iteration starts from the current u
+    const bool warm = A.warm != 0 || (d.flags & 1) != 0;
     for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                if (m > 0 && C.hasP) {
+                if ((m > 0 || warm) && C.hasP) {
                     const double2 u = A.u[base + (int64_t)b * nxl + a];
                     p[a][b] = (Real)u.x;
                     pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
@@ -930,7 +934,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
                 vr[a][b] = k0 * p[a][b];
                 vi[a][b] = kh0 * pd[a][b];
             }
-        if (C.hasE) slot_init(e, A, d, m > 0, k0, kh0);
+        if (C.hasE) slot_init(e, A, d, m > 0 || warm, k0, kh0);
 
         for (int nu = 1; nu < nt; ++nu) {
             const int par = nu & 1;
@@ -1058,7 +1062,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
                     const double ur = d.two_over_nt * (double)vr[a][b];
                     const double ui = d.two_over_nt * (double)vi[a][b];
                     double orr = 0.0, oi = 0.0;
-                    if (m > 0) {
+                    if (m > 0 || warm) {
                         const double2 o = A.u[n];
                         orr = o.x;
                         oi = o.y;
@@ -1068,7 +1072,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
                     A.u[n] = make_double2(ur, ui);
                 }
         }
-        if (C.hasE) slot_finish(e, A, d, m > 0, dsum, nsum);
+        if (C.hasE) slot_finish(e, A, d, m > 0 || warm, dsum, nsum);
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
@@ -1237,8 +1241,10 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
     int it = 0;
     const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    // warm start: the first WaveHoltz iteration starts from the current u
+    const bool warm = A.warm != 0 || (d.flags & 1) != 0;
     for (int m = 0; m < max_wh; ++m) {
-        if (C.has) slot_init(s, A, d, m > 0, TAB[2], TAB[3]);
+        if (C.has) slot_init(s, A, d, m > 0 || warm, TAB[2], TAB[3]);
         for (int nu = 1; nu < nt; ++nu) {
             Real* buf = (nu & 1) ? C.buf1 : C.buf0;
             const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
@@ -1255,7 +1261,7 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
             }
         }
         double dsum = 0.0, nsum = 0.0;
-        if (C.has) slot_finish(s, A, d, m > 0, dsum, nsum);
+        if (C.has) slot_finish(s, A, d, m > 0 || warm, dsum, nsum);
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
@@ -1536,6 +1542,8 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     int it = 0;
     const int max_wh = d.max_wh > 0 ? d.max_wh : A.max_wh;
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
+    // warm start: the first WaveHoltz iteration starts from the current u
+    const bool warm = A.warm != 0 || (d.flags & 1) != 0;
     for (int m = 0; m < max_wh; ++m) {
         // u -> (p^1, pdot^{1/2}, v)
         {
@@ -1543,7 +1551,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             int il = tid % nxl, jl = tid / nxl;
             for (int n = tid; n < nloc; n += bd) {
                 Real p = Real(0), pd = Real(0);
-                if (m > 0) {
+                if (m > 0 || warm) {
                     const double2 u = A.u[d.node_off + n];
                     p = (Real)u.x;
                     pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
@@ -1565,10 +1573,10 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             const Quad<Real> tb{TAB[4 * nu + 0], TAB[4 * nu + 1], TAB[4 * nu + 2], TAB[4 * nu + 3]};
             if (nu < nt - 1)
                 stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
-                                            A, d, m > 0, dsum, nsum);
+                                            A, d, m > 0 || warm, dsum, nsum);
             else
                 stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
-                                           A, d, m > 0, dsum, nsum);
+                                           A, d, m > 0 || warm, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
         it = m + 1;

@@ -253,6 +253,7 @@ struct SweepReq {
     int prec;
     double tau;
     int max_wh;
+    bool warm;
     bool done = false;
     int rc = 0;
 };
@@ -337,7 +338,8 @@ struct dd_handle {
     // placement in the store
     Store* store = nullptr;
     bool own_store = false;
-    bool batched = false;            // sweeps go through the store's rendezvous
+    bool batched = false;            // sweeps go through the store's batched launches
+    bool sweep_warm = false;         // the next sweeps start WaveHoltz from the current u
     int64_t node_base = 0, if_base = 0, item_base = 0, tab_base = 0, w1d_base = 0, wsp_base = 0;
     int64_t node_len = 0, if_len = 0, item_len = 0, tab_len = 0, w1d_len = 0, wsp_len = 0;
     bool placed = false;
@@ -416,6 +418,7 @@ wdd::SweepArgs<Real> make_args(dd_handle* h, const double2* g_in, double2* g_out
     a.desc = h->store->d_desc.p + h->item_base;
     a.n_items = (int)h->L;
     a.wh_iters = h->store->d_iters.p + h->item_base;
+    a.warm = h->sweep_warm ? 1 : 0;
     a.lds_bytes = h->lds[sizeof(Real) == 4 ? 1 : 0];
     a.nt_max = h->nt_max;
     return a;
@@ -621,6 +624,7 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
             wdd::SubDesc d = q->h->desc[it.l];
             d.max_wh = q->max_wh;
             d.tau = q->tau;
+            d.flags = q->warm ? 1 : 0;
             hw[total + (int64_t)i] = d;
         }
         for (const Item& it : g.items)
@@ -700,7 +704,7 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
     HIPCHK(hipStreamSynchronize(h->stream));
     Store* S = h->store;
     Sched& Q = S->sched;
-    SweepReq req{h, g_in, g_out, src, with_f, prec, tau, max_wh};
+    SweepReq req{h, g_in, g_out, src, with_f, prec, tau, max_wh, h->sweep_warm};
     std::unique_lock<std::mutex> lk(Q.mu);
     Q.pending.push_back(&req);
     while (!req.done) {
@@ -873,20 +877,38 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
     return DD_OK;
 }
 
-// Plain fixed-point iteration G <- T G + h.
-int fixed_point(dd_handle* h, double tol, int max_iter, double hnorm) {
+// Plain fixed-point iteration G <- T G + h.  With warm start the sweep
+// is taken as sweep(G + g_phys, sources on) (= T G + h, the sweep being
+// affine), so consecutive sweeps solve converging subdomain problems and
+// each WaveHoltz solve starts from the previous sweep's u.
+int residual_sweep(dd_handle* h, bool with_f, int prec, double tau, double hnorm, double* rel);
+
+int fixed_point(dd_handle* h, bool with_f, double tol, int max_iter, double hnorm) {
     const int64_t n = h->n_if;
     HIPCHK(hipMemsetAsync(h->d_G.p, 0, sizeof(double2) * n, h->stream));
     h->st.outer_iters = 0;
     h->st.rel_residual = hnorm == 0.0 ? 0.0 : 1.0;
     if (hnorm == 0.0) return DD_OK;
+    const bool warm = h->opt.warm != 0;
     for (int it = 0; it < max_iter; ++it) {
-        CHK(run_sweep(h, h->d_G.p, h->d_tmp.p, 0.0, false, true));
-        CHK(axpby(h, cplx(1.0), h->d_h.p, cplx(1.0), h->d_tmp.p));   // tmp = T G + h
-        CHK(axpby(h, cplx(1.0), h->d_tmp.p, cplx(-1.0), h->d_G.p));  // G = tmp - G
-        const double d = norm(h, h->d_G.p);
-        HIPCHK(hipMemcpyAsync(h->d_G.p, h->d_tmp.p, sizeof(double2) * n, hipMemcpyDeviceToDevice,
-                              h->stream));
+        double d = 0.0;
+        if (warm) {
+            // tmp = T G + h - G (u left for the next warm start), G += tmp
+            h->sweep_warm = true;   // the h-sweep (or previous iteration) left u
+            double rel = 0.0;
+            const int rc = residual_sweep(h, with_f, h->opt.precision, h->opt.tau_in, hnorm, &rel);
+            h->sweep_warm = false;
+            CHK(rc);
+            CHK(axpby(h, cplx(1.0), h->d_tmp.p, cplx(1.0), h->d_G.p));
+            d = rel * hnorm;
+        } else {
+            CHK(run_sweep(h, h->d_G.p, h->d_tmp.p, 0.0, false, true));
+            CHK(axpby(h, cplx(1.0), h->d_h.p, cplx(1.0), h->d_tmp.p));   // tmp = T G + h
+            CHK(axpby(h, cplx(1.0), h->d_tmp.p, cplx(-1.0), h->d_G.p));  // G = tmp - G
+            d = norm(h, h->d_G.p);
+            HIPCHK(hipMemcpyAsync(h->d_G.p, h->d_tmp.p, sizeof(double2) * n,
+                                  hipMemcpyDeviceToDevice, h->stream));
+        }
         h->st.outer_iters = it + 1;
         h->st.rel_residual = d / hnorm;
         if (!std::isfinite(d)) return fail(DD_ENAN, "non-finite outer residual");
@@ -978,10 +1000,13 @@ int solve_core(dd_handle* h, bool with_f, double tol, int max_iter) {
     CHK(run_sweep(h, h->d_g0.p, h->d_h.p, 1.0, with_f, true));  // h = sweep(g_phys, src)
     const double hnorm = norm(h, h->d_h.p);
     if (!std::isfinite(hnorm)) return fail(DD_ENAN, "non-finite right-hand side");
-    CHK(fixed_point(h, tol, max_iter, hnorm));
+    CHK(fixed_point(h, with_f, tol, max_iter, hnorm));
     // final sweep with G + g_phys and sources: u, and T G + h for the true residual
     double rel = 0.0;
-    CHK(residual_sweep(h, with_f, h->opt.precision, h->opt.tau_in, hnorm, &rel));
+    h->sweep_warm = h->opt.warm != 0;
+    const int rc = residual_sweep(h, with_f, h->opt.precision, h->opt.tau_in, hnorm, &rel);
+    h->sweep_warm = false;
+    CHK(rc);
     h->st.true_rel_residual = rel;
     h->has_state = true;
     return DD_OK;
@@ -1114,6 +1139,7 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
         return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
     if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
     if (!(o.relax >= 0.0) || !std::isfinite(o.relax)) return fail(DD_EINVAL, "relax must be >= 0");
+    if (o.warm != 0 && o.warm != 1) return fail(DD_EINVAL, "warm must be 0 or 1");
     const int P = degree;
     const int Nx = mesh->nx * P + 1, Ny = mesh->ny * P + 1;
     const int64_t N = (int64_t)Nx * Ny;
@@ -1630,6 +1656,7 @@ int dd_default_options(dd_options* o) {
     o->cfl = 0.9;
     o->refine = 4;
     o->relax = 0.0;
+    o->warm = 0;
     return DD_OK;
 }
 
@@ -2240,7 +2267,7 @@ int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, doub
     for (dd_handle* h : b->probs) {
         HIPCHK(hipStreamSynchronize(h->stream));
         reqs.push_back(SweepReq{h, h->d_G.p, h->d_tmp.p, 0.0, false, h->opt.precision, 0.0,
-                                fixed_iters});
+                                fixed_iters, false});
     }
     std::vector<SweepReq*> rp;
     for (auto& r : reqs) rp.push_back(&r);

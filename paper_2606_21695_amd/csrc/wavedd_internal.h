@@ -30,6 +30,8 @@ struct SubDesc {
     double sx_ref, sy_ref;  // 2/hx, 2/hy: reference-to-physical stiffness scales
     int64_t ws_off;      // STREAM layout: first element of its two zero-padded p grids
     double tau;          // see max_wh
+    int flags;           // bit 0: warm start (first WaveHoltz iteration from the current u)
+    int pad1;
 };
 
 // Per-node coefficient arrays of a sweep in the sweep precision `Real`.
@@ -58,6 +60,7 @@ struct SweepArgs {
     double2* g_out;          // updated interface data
     double src;              // multiplier of the source term
     double2* u;              // WaveHoltz iterate / result per node (FP64 complex)
+    int warm;                // 1: the first WaveHoltz iteration starts from u (else from 0)
     int* wh_iters;           // per item: WaveHoltz iterations performed
     double tau;              // inner tolerance (<= 0: fixed count)
     int max_wh;              // iteration cap / fixed count

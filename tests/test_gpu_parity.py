@@ -395,3 +395,34 @@ def test_state_roundtrip(gpu_lib):
     W.dd_set_state(h, G)
     assert np.array_equal(W.dd_get_state(h), G)
     W.dd_destroy(h)
+
+
+@pytest.mark.parametrize("layout", [0, 4])
+def test_fixed_point_warm_start(gpu_lib, layout):
+    """Fixed-point outer iteration, cold and warm-started WaveHoltz, on a
+    strip partition (no interior cross points, so I - T has no null mode and
+    the fixed point converges): the cold run follows the oracle's fixed-point
+    iteration; both reach the global LU solution to the outer tolerance's
+    accuracy; warm starts need far fewer WaveHoltz iterations."""
+    W = gpu_lib
+    nx, ny, P, sx, sy, om, tol = 8, 8, 1, 2, 1, 6.0, 1e-8   # converges in ~480 iterations
+
+    def src(X, Y):
+        return np.exp(-((X - 0.3) ** 2 + (Y - 0.6) ** 2) / (2 * 0.05 ** 2))
+    out = {}
+    for warm in (0, 1):
+        h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, outer=W.DD_OUTER_FIXED, warm=warm,
+                           tau_in=1e-12, layout=layout)
+        u, st, rc = W.dd_solve(h, src(Xl, Yl), None, tol, max_iter=5000)
+        W.dd_destroy(h)
+        out[warm] = (u, st)
+        print(f"fixed point warm={warm} iters={st['outer_iters']} "
+              f"wh_total={st['wh_iters_total']}", flush=True)
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, om, _cwave)
+    us_ref, info = dd.solve_dd(dec, src(X, Y), tol=tol, method="fixed", max_iter=5000)
+    u_lu = sem.solve(dec.mesh, _cwave(X, Y), om, src(X, Y))
+    assert abs(out[0][1]["outer_iters"] - info["iters"]) <= 1
+    for warm in (0, 1):
+        assert _rel([out[warm][0]], [u_lu]) < 1e-6
+        assert out[warm][1]["true_rel_residual"] <= 2 * tol
+    assert out[1][1]["wh_iters_total"] < 0.5 * out[0][1]["wh_iters_total"]
