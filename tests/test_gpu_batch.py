@@ -180,3 +180,53 @@ def test_engine_admission_under_a_small_budget(gpu_lib):
         assert ei.value.code == W.DD_ENOMEM
     finally:
         W.dd_engine_destroy(e)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_batch_sampled(gpu_lib, prec):
+    """The 400-subdomain batch (58 problems, P 1..4, 8..64 elements per
+    subdomain side) set up as the benchmark does, one layout per shape from
+    the autotuner: for one problem of each layout in use, one sweep of two
+    fixed WaveHoltz iterations from random interface data, a corner and the
+    last subdomain recomputed by the oracle's WaveHoltz."""
+    import workloads
+    from oracle import waveholtz as wh
+    W = gpu_lib
+    wls = workloads.c4()
+    specs = [W.workload_spec(wl) for wl in wls]
+    m = 2
+    b = W.dd_batch_setup(specs, W.dd_default_options(precision=prec, tau_in=0.0, max_wh=m))
+    try:
+        lays = [W.dd_layout(W.dd_batch_handle(b, i))[0] for i in range(len(wls))]
+        picks = sorted({lay: i for i, lay in reversed(list(enumerate(lays)))}.values())
+        print(f"layouts {sorted(set(lays))} picks {picks}", flush=True)
+        for i in picks:
+            wl, s = wls[i], specs[i]
+            h = W.dd_batch_handle(b, i)
+            sz = W.dd_sizes(h)
+            rng = np.random.default_rng(100 + i)
+            g = rng.standard_normal(sz["n_iface"]) + 1j * rng.standard_normal(sz["n_iface"])
+            g_gpu, u_gpu, its = W.dd_sweep(h, g, s["f"], 1.0)
+            assert (its == m).all()
+            mesh = sem.Rect(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+            X, Y = sem.node_coords(mesh)
+            c, f = wl.c(X, Y), wl.f(X, Y)
+            mx, my = wl.nx // wl.sx, wl.ny // wl.sy
+            nxl, nyl = mx * wl.P + 1, my * wl.P + 1
+            per, nloc = 2 * nxl + 2 * nyl, sz["n_local"]
+            for l in sorted({0, wl.sx * wl.sy - 1}):
+                a_, b_ = l % wl.sx, l // wl.sx
+                x0, y0 = wl.x0 + a_ * mx * mesh.hx, wl.y0 + b_ * my * mesh.hy
+                sub = sem.Rect(mx, my, wl.P, x0, x0 + mx * mesh.hx, y0, y0 + my * mesh.hy)
+                ii = a_ * mx * wl.P + np.arange(nxl)
+                jj = b_ * my * wl.P + np.arange(nyl)
+                gl = (jj[:, None] * mesh.Nx + ii[None, :]).ravel()
+                one = dd.Decomposition(sub, dd.Partition(1, 1), c[gl], wl.omega)
+                rhs = one.rhs(0, np.asarray(f[gl], dtype=float), g[l * per:(l + 1) * per], 1.0)
+                sd = one.subs[0]
+                nt = wh.subdomain_steps(one)[0]
+                u_ref, _ = wh.solve(sd["A"], sd["M"], sd["H"], rhs, wl.omega, nt, fixed_iters=m)
+                err = np.linalg.norm(u_gpu[l * nloc:(l + 1) * nloc] - u_ref) / np.linalg.norm(u_ref)
+                assert err < (1e-11 if prec == 0 else 1e-4), (i, l, lays[i], err)
+    finally:
+        W.dd_batch_destroy(b)

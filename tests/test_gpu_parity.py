@@ -426,3 +426,73 @@ def test_fixed_point_warm_start(gpu_lib, layout):
         assert _rel([out[warm][0]], [u_lu]) < 1e-6
         assert out[warm][1]["true_rel_residual"] <= 2 * tol
     assert out[1][1]["wh_iters_total"] < 0.5 * out[0][1]["wh_iters_total"]
+
+
+def _oracle_sub(wl, mesh, l, c, f, g_l, nxl, nyl, mx, my):
+    """The oracle's system for subdomain l of a workload alone (a 1x1
+    decomposition of its rectangle) and its right-hand side."""
+    a, b = l % wl.sx, l // wl.sx
+    x0, y0 = wl.x0 + a * mx * mesh.hx, wl.y0 + b * my * mesh.hy
+    sub = sem.Rect(mx, my, wl.P, x0, x0 + mx * mesh.hx, y0, y0 + my * mesh.hy)
+    i = a * mx * wl.P + np.arange(nxl)
+    j = b * my * wl.P + np.arange(nyl)
+    gl = (j[:, None] * mesh.Nx + i[None, :]).ravel()
+    one = dd.Decomposition(sub, dd.Partition(1, 1), c[gl], wl.omega)
+    b_l = one.rhs(0, np.asarray(f[gl], dtype=float), g_l, 1.0)
+    return one, b_l
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c2_full_size_sweep_sampled(gpu_lib, prec):
+    """The 256x256-element P=3 waveguide with 16x16 subdomains at full size,
+    in the autotuned layout the benchmark uses: one sweep of three fixed
+    WaveHoltz iterations from random interface data; sampled subdomains
+    (corner, edge, waveguide, interior) recomputed one by one by the
+    oracle's WaveHoltz."""
+    import workloads
+    W = gpu_lib
+    wl = workloads.c2()
+    m = 3
+    h, Xl, Yl = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, precision=prec,
+                       tau_in=0.0, max_wh=m)
+    sizes = W.dd_sizes(h)
+    nloc, n_if = sizes["n_local"], sizes["n_iface"]
+    rng = np.random.default_rng(22)
+    g = rng.standard_normal(n_if) + 1j * rng.standard_normal(n_if)
+    print(f"c2 sweep prec={prec} layout={W.dd_layout(h)}", flush=True)
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, wl.f(Xl, Yl), 1.0)
+    W.dd_destroy(h)
+    assert (its == m).all()
+    mesh = sem.Rect(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+    mx, my = wl.nx // wl.sx, wl.ny // wl.sy
+    nxl, nyl = mx * wl.P + 1, my * wl.P + 1
+    per = 2 * nxl + 2 * nyl
+    X, Y = sem.node_coords(mesh)
+    c, f = wl.c(X, Y), wl.f(X, Y)
+    tol = 1e-11 if prec == 0 else 1e-4
+    for l in (0, 7, 8 + 16 * 2, 8 + 16 * 9, 255):
+        one, b_l = _oracle_sub(wl, mesh, l, c, f, g[l * per:(l + 1) * per], nxl, nyl, mx, my)
+        sd = one.subs[0]
+        nt = wh.subdomain_steps(one)[0]
+        u_ref, _ = wh.solve(sd["A"], sd["M"], sd["H"], b_l, wl.omega, nt, fixed_iters=m)
+        assert _rel([u_gpu[l * nloc:(l + 1) * nloc]], [u_ref]) < tol, l
+
+
+def test_c2_full_size_solve_global_residual(gpu_lib):
+    """The benchmark's solve (256x256 elements, FP64, tol 1e-8) at full size:
+    the oracle's own assembled operator S measures the glued solution's
+    global residual ||b - S u|| / ||b||; the interface residual meets tol."""
+    import workloads
+    W = gpu_lib
+    wl = workloads.c2()
+    h, Xl, Yl = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, tau_in=wl.tau_in)
+    u, st, rc = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, max_iter=2000)
+    W.dd_destroy(h)
+    mesh = sem.Rect(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+    X, Y = sem.node_coords(mesh)
+    S, _, _, _ = sem.system(mesh, wl.c(X, Y), wl.omega)
+    b = sem.load(mesh, wl.f(X, Y))
+    res = np.linalg.norm(b - S @ u) / np.linalg.norm(b)
+    print(f"c2 solve iters={st['outer_iters']} global residual {res:.2e}", flush=True)
+    assert st["true_rel_residual"] <= wl.tol
+    assert res < 5 * wl.tol
