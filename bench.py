@@ -99,18 +99,26 @@ def cpu_baseline(wl, seconds=12.0):
                       f"one thread ({el:.1f} s; oracle setup {setup_s:.1f} s not counted)"}
 
 
-def variants(W, wl, u_ref, _unused, steps=2):
+VARIANTS = {"fp32_refined": ("fp32", 1e-6, 0.0), "fp64_relaxed": ("fp64", None, 0.1),
+            "fp32_refined_relaxed": ("fp32", 1e-6, 0.1)}
+
+
+def variants(W, wl, u_ref, names, max_wh, progress=0, steps=2):
     """FP32 sweeps (with FP64 refinement) and relaxed inner tolerance on the
     same workload: solves/s, latency, DOF-updates/s and the relative L2
-    difference from the strict FP64 solution."""
+    difference from the main run's solution."""
     import torch
     out = {}
     N = u_ref.size
     dev = torch.device("cuda:0")
-    for name, prec, tau, relax in (("fp32_refined", W.DD_FP32, 1e-6, 0.0),
-                                   ("fp64_relaxed", W.DD_FP64, wl.tau_in, 0.1),
-                                   ("fp32_refined_relaxed", W.DD_FP32, 1e-6, 0.1)):
-        prob = W.Problem(wl, precision=prec, tau_in=tau, relax=relax)
+    for name in names:
+        pname, tau, relax = VARIANTS[name]
+        prec = W.DD_FP64 if pname == "fp64" else W.DD_FP32
+        tau = wl.tau_in if tau is None else tau
+        prob = W.Problem(wl, precision=prec, tau_in=tau, relax=relax, max_wh=max_wh)
+        if progress:
+            W.dd_set_progress(prob.h, lambda it, rel, n=name: log(f"  {n} outer {it}: {rel:.2e}"),
+                              progress)
         f_re = torch.from_numpy(prob.f).to(dev)
         u_re = torch.empty(N, dtype=torch.float64, device=dev)
         u_im = torch.empty(N, dtype=torch.float64, device=dev)
@@ -382,6 +390,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated comparison solves (default: all three for the "
+                         "256x256 workloads, fp32_refined_relaxed for 512x512)")
+    ap.add_argument("--progress", type=int, default=None,
+                    help="print the outer residual every N iterations (default: 25 for "
+                         "512x512, off otherwise)")
     ap.add_argument("--serve", action="store_true", help="serving engine on the c5 stream")
     ap.add_argument("--max-wh", type=int, default=None,
                     help="WaveHoltz cap per subdomain solve (default: the library's 100 for "
@@ -436,6 +450,10 @@ def main():
     t0 = time.perf_counter()
     prob = W.Problem(wl, precision=prec, tau_in=tau, relax=args.relax, max_wh=args.max_wh)
     setup_s = time.perf_counter() - t0
+    if args.progress is None:
+        args.progress = 25 if args.config == "c3" else 0
+    if args.progress:
+        W.dd_set_progress(prob.h, lambda it, rel: log(f"  outer {it}: {rel:.2e}"), args.progress)
     h = prob.h
     sizes = W.dd_sizes(h)
     N = sizes["n_global"]
@@ -520,7 +538,10 @@ def main():
             "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None}),
     }
     if not args.no_variants:
-        out["variants"] = variants(W, wl, u, lambda: None)
+        names = (args.variants.split(",") if args.variants else
+                 ["fp32_refined_relaxed"] if args.config == "c3" else list(VARIANTS))
+        out["variants"] = variants(W, wl, u, names, args.max_wh, args.progress,
+                                   steps=min(2, args.steps))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     prob.close()

@@ -215,6 +215,14 @@ int dd_set_state(dd_handle* h, const double* G);
  * one launch (sum over subdomains of nloc*(N_t-1)*iterations; may be NULL). */
 int dd_time_sweep(dd_handle* h, int reps, int fixed_iters, double* ms, double* dof_updates);
 
+/* Progress report of a running solve: called on the solving thread every
+ * `every` outer iterations with the iteration count and the current
+ * relative outer residual (the GMRES estimate, or the fixed-point update).
+ * fn = NULL switches it off.  The callback must not call back into the
+ * handle. */
+typedef void (*dd_progress_fn)(void* user, int outer_iters, double rel_residual);
+int dd_set_progress(dd_handle* h, dd_progress_fn fn, void* user, int every);
+
 /* Layout in use (DD_LAYOUT_NODE .. DD_LAYOUT_STREAM) and threads/workgroup. */
 int dd_layout(const dd_handle* h, int* layout, int* wg_threads);
 

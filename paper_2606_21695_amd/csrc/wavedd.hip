@@ -340,6 +340,11 @@ struct dd_handle {
     bool own_store = false;
     bool batched = false;            // sweeps go through the store's batched launches
     bool sweep_warm = false;         // the next sweeps start WaveHoltz from the current u
+    dd_progress_fn prog = nullptr;   // progress report (dd_set_progress)
+    void* prog_user = nullptr;
+    int prog_every = 1;
+    int prog_base = 0;               // outer iterations before the current GMRES pass
+    double prog_scale = 1.0;         // pass residual -> residual relative to ||h||
     int64_t node_base = 0, if_base = 0, item_base = 0, tab_base = 0, w1d_base = 0, wsp_base = 0;
     int64_t node_len = 0, if_len = 0, item_len = 0, tab_len = 0, w1d_len = 0, wsp_len = 0;
     bool placed = false;
@@ -849,6 +854,8 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
             g[j] = cs[j] * g[j];
             rel = std::abs(g[j + 1]) / rnorm0;
             k = j + 1;
+            if (h->prog && its % h->prog_every == 0)
+                h->prog(h->prog_user, h->prog_base + its, rel * h->prog_scale);
             if (!std::isfinite(rel)) return fail(DD_ENAN, "non-finite outer residual");
             if (rel <= tol || its >= max_iter || hn == 0.0) break;
         }
@@ -911,6 +918,7 @@ int fixed_point(dd_handle* h, bool with_f, double tol, int max_iter, double hnor
         }
         h->st.outer_iters = it + 1;
         h->st.rel_residual = d / hnorm;
+        if (h->prog && (it + 1) % h->prog_every == 0) h->prog(h->prog_user, it + 1, d / hnorm);
         if (!std::isfinite(d)) return fail(DD_ENAN, "non-finite outer residual");
         if (d <= tol * hnorm) break;
     }
@@ -974,6 +982,8 @@ int solve_gmres_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
         const double inner = fp32 ? std::max(1e-4, want) : want;
         int its = 0;
         double irel = 0.0;
+        h->prog_base = its_total;
+        h->prog_scale = hnorm > 0.0 ? rnorm / hnorm : 0.0;
         CHK(gmres(h, h->d_res.p, h->d_D.p, rnorm, inner, max_iter - its_total, &its, &irel));
         its_total += its;
         last_rec = irel * rnorm / hnorm;
@@ -1764,6 +1774,15 @@ int dd_mesh_coords(const dd_mesh* mesh, int degree, double* x, double* y) {
             x[(int64_t)j * Nx + i] = xs[i];
             y[(int64_t)j * Nx + i] = ys[j];
         }
+    return DD_OK;
+}
+
+int dd_set_progress(dd_handle* h, dd_progress_fn fn, void* user, int every) {
+    CHK(validate_handle(h));
+    if (fn && every < 1) return fail(DD_EINVAL, "every must be >= 1");
+    h->prog = fn;
+    h->prog_user = user;
+    h->prog_every = fn ? every : 1;
     return DD_OK;
 }
 

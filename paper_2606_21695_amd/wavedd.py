@@ -30,7 +30,7 @@ EXPORTS = [
     "dd_batch_time_sweep", "dd_batch_launches", "dd_batch_wait_progress",
     "dd_batch_solve_start", "dd_batch_solve_finish",
     "dd_engine_create", "dd_engine_destroy", "dd_engine_submit", "dd_engine_status",
-    "dd_engine_wait", "dd_engine_get_info", "dd_engine_wait_any",
+    "dd_engine_wait", "dd_engine_get_info", "dd_engine_wait_any", "dd_set_progress",
 ]
 DD_REQ_QUEUED, DD_REQ_RUNNING, DD_REQ_DONE = 0, 1, 2
 
@@ -75,6 +75,10 @@ class dd_engine_info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# void (*)(void* user, int outer_iters, double rel_residual)
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.c_double)
 
 
 class WaveddError(RuntimeError):
@@ -161,6 +165,7 @@ def load():
         "dd_engine_wait": ([P, C.c_int64, D, D, C.POINTER(dd_stats), D], C.c_int),
         "dd_engine_get_info": ([P, C.POINTER(dd_engine_info)], C.c_int),
         "dd_engine_wait_any": ([P, I64], C.c_int),
+        "dd_set_progress": ([P, PROGRESS_FN, P, C.c_int], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -245,6 +250,22 @@ def dd_time_steps(h):
     out = (C.c_int * n)()
     _check(load().dd_time_steps(h, out))
     return np.array(out[:], dtype=np.int64)
+
+
+_progress_keep = {}
+
+
+def dd_set_progress(h, fn=None, every=10):
+    """Call fn(outer_iters, rel_residual) every `every` outer iterations of
+    the handle's solves (fn=None switches it off)."""
+    key = h.value
+    if fn is None:
+        _check(load().dd_set_progress(h, PROGRESS_FN(), None, 1))
+        _progress_keep.pop(key, None)
+        return
+    cb = PROGRESS_FN(lambda _u, it, rel: fn(it, rel))
+    _progress_keep[key] = cb   # keep the thunk alive while the library holds it
+    _check(load().dd_set_progress(h, cb, None, every))
 
 
 def dd_layout(h):
