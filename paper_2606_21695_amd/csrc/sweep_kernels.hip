@@ -1504,7 +1504,7 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
     }
 }
 
-template <typename Real, int P, bool HAS_SRC>
+template <typename Real, int P>
 __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
                                   double* red) {
     constexpr int W = 2 * P + 1;
@@ -1589,14 +1589,14 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     if (threadIdx.x == 0) A.wh_iters[item] = it;
 }
 
-template <typename Real, int P, bool HAS_SRC>
+template <typename Real, int P>
 __global__ void __launch_bounds__(kStreamWG) sweep_stream_kernel(const SweepArgs<Real> A) {
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
         const SubDesc d = A.desc[item];
-        sweep_stream_item<Real, P, HAS_SRC>(A, d, item, lds, red);
+        sweep_stream_item<Real, P>(A, d, item, lds, red);
         __syncthreads();
     }
 }
@@ -1788,15 +1788,9 @@ template hipError_t launch_apply_node<float>(const SweepArgs<float>&, int, int, 
 template <typename Real>
 hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
     const size_t lds = a.lds_bytes;
-    const bool src = a.Fre != nullptr && a.src != 0.0;
     if (wg > kStreamWG) return hipErrorInvalidValue;
-#define L(PP)                                                                                    \
-    if (src)                                                                                     \
-        hipLaunchKernelGGL((sweep_stream_kernel<Real, PP, true>), dim3(a.n_items), dim3(wg), lds, \
-                           s, a);                                                                \
-    else                                                                                         \
-        hipLaunchKernelGGL((sweep_stream_kernel<Real, PP, false>), dim3(a.n_items), dim3(wg),     \
-                           lds, s, a)
+#define L(PP) \
+    hipLaunchKernelGGL((sweep_stream_kernel<Real, PP>), dim3(a.n_items), dim3(wg), lds, s, a)
     WDD_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();

@@ -304,10 +304,8 @@ struct Store {
     DBuf<int> d_work_iters;
     wdd::SubDesc* h_work = nullptr;  // pinned staging of the work lists (per slot)
     int* h_work_iters = nullptr;
-    hipStream_t stream = nullptr;
-    hipStream_t ss[Sched::kSlots] = {};   // launch slot streams
+    hipStream_t ss[Sched::kSlots] = {};   // launch slot streams (shared stores)
     hipEvent_t sev0[Sched::kSlots] = {}, sev1[Sched::kSlots] = {};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t bytes = 0;
     std::mutex mu;            // allocators, layout cache
     std::map<std::tuple<int, int, int, int>, int> layout_cache;  // (mx, my, P, prec) -> layout
@@ -1374,7 +1372,6 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
 void store_destroy(Store* S) {
     if (!S) return;
     (void)hipSetDevice(S->dev);
-    if (S->stream) (void)hipStreamSynchronize(S->stream);
     for (auto& B : S->pb) {
         B.coef.free();
         B.tab.free();
@@ -1393,9 +1390,6 @@ void store_destroy(Store* S) {
         if (S->sev1[i]) (void)hipEventDestroy(S->sev1[i]);
         if (S->ss[i]) (void)hipStreamDestroy(S->ss[i]);
     }
-    if (S->ev0) (void)hipEventDestroy(S->ev0);
-    if (S->ev1) (void)hipEventDestroy(S->ev1);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
 }
 
@@ -1462,9 +1456,6 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
             bytes += 4 * (cwsp + wdd::kStreamRecord * cn);
         }
     }
-    STCHK(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
-    STCHK(hipEventCreate(&S->ev0));
-    STCHK(hipEventCreate(&S->ev1));
     if (shared) {
         STCHK(S->d_gin.alloc(ci));
         STCHK(S->d_gout.alloc(ci));
