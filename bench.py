@@ -32,7 +32,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 # kernel's source (its layout section plus the shared helpers) and the run;
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    ("e901ef5d2ff97435", "solve", "c2", "fp64"): round((15289.7 * 2.0 + 15423.7) * 1024),
+    ("28534c7ad0307332", "solve", "c2", "fp64"): round((15275.8 * 2.0 + 22263.8) * 1024),
     ("56d22eeacc7fb5c3", "protocol", "c3", "fp64"): round((57463302.4 * 2.0 + 63327220.4) * 1024),
     ("56d22eeacc7fb5c3", "protocol", "c3", "fp32"): round((28810021.6 * 2.0 + 31881872.7) * 1024),
 }
@@ -42,6 +42,9 @@ _SECTIONS = {1: ("// NODE layout (one DOF per thread)", "// STREAM layout"),
              2: ("// PATCH layout, one barrier per step", "// NODE layout (one DOF per thread)"),
              3: ("// PATCH layout\n", "// PATCH layout, one barrier per step"),
              4: ("// STREAM layout", "}  // namespace\n")}
+LAYOUT_NAMES = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}
+KERNEL_NAMES = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
+                4: "sweep_stream_kernel"}
 
 
 def kernel_hash(layout):
@@ -351,9 +354,8 @@ def protocol_bench(args):
         lay, wg = W.dd_layout(h)
         traffic = MEASURED_TRAFFIC.get((kernel_hash(lay), "protocol", args.config, args.precision))
         prob.close()
-        layout = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay]
-        kernel = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
-                  4: "sweep_stream_kernel"}[lay]
+        layout = LAYOUT_NAMES[lay]
+        kernel = KERNEL_NAMES[lay]
         desc = (f"{args.config}: {wl.nx}x{wl.ny} elements P={wl.P}, {wl.sx}x{wl.sy} subdomains, "
                 f"omega={wl.omega:.2f}")
         flop = flops_per_update(wl.P) * dof
@@ -516,7 +518,7 @@ def main():
         "config": {"workload": f"{args.config}: {wl.nx}x{wl.ny} elements P={P}, "
                                f"{wl.sx}x{wl.sy} subdomains, omega={wl.omega:.2f}, tol={wl.tol}",
                    "precision": args.precision,
-                   "layout": {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}[lay],
+                   "layout": LAYOUT_NAMES[lay],
                    "wg_threads": wg, "tau_in": tau, "relax": args.relax, "max_wh": args.max_wh},
         "solves_per_s": args.steps / total,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
@@ -532,8 +534,7 @@ def main():
         "roofline": dict(roof, **{
             "traffic": MEASURED_TRAFFIC.get((kernel_hash(lay), "solve", args.config,
                                              args.precision)),
-            "kernel": {1: "sweep_node_kernel", 2: "sweep_patch1_kernel",
-                       3: "sweep_patch_kernel", 4: "sweep_stream_kernel"}[lay],
+            "kernel": KERNEL_NAMES[lay],
             "flop_per_dof_update": fl,
             "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None}),
     }

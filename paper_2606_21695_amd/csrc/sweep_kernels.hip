@@ -253,9 +253,11 @@ __device__ __forceinline__ void window_coeffs(Real (&w)[2 * P + 1], int k, int n
 // PATCH layout
 // ---------------------------------------------------------------------------
 
-// LDS carve-up of the patch layout (in units of Real).  The edge lines GC
-// (right column) and GR (top row) carry kMaxP zeros on both ends so their
-// windows need no bounds checks.
+// LDS carve-up of the patch layout (in units of Real).  VC, VR, SX, SY hold
+// P planes of one value per element (plane k of element e at k * mx*my + e),
+// so a wave's lanes touch consecutive words.  The edge lines GC (right
+// column) and GR (top row) carry kMaxP zeros on both ends so their windows
+// need no bounds checks.
 struct PatchLds {
     int vc, vr, sx, sy, gc, gr, zr, corner, sink, kl, tab, total;
 };
@@ -297,8 +299,12 @@ struct PatchCtx {
     bool hasP, hasE;
     int ex, ey;
     Real* VC; Real* VR; Real* SX; Real* SY; Real* GC; Real* GR; Real* CORN; const Real* TAB;
+    // neighbour lines and the strides between their entries (mx*my between
+    // planes, 1 along an edge line, 0 on the zero line and the sink)
     const Real* pR; const Real* pT; const Real* pL; const Real* pB;
+    int sR, sT, sL, sB;
     Real* wVC; Real* wVR; Real* wSX; Real* wSY;  // own publish targets (a sink without a patch)
+    int sW;
     // edge slot
     bool e_col, e_corner, e_wcorner;
     int ek, e_il, e_jl;
@@ -332,15 +338,20 @@ struct PatchCtx {
         ex = hasP ? tid % mx : 0;
         ey = hasP ? tid / mx : 0;
         const int t = hasP ? tid : 0;
-        pR = (ex + 1 < mx) ? VC + (t + 1) * P : GC + ey * P;
-        pT = (ey + 1 < my) ? VR + (t + mx) * P : GR + ex * P;
-        pL = (ex > 0) ? SX + (t - 1) * P : ZR;
-        pB = (ey > 0) ? SY + (t - mx) * P : ZR;
+        pR = (ex + 1 < mx) ? VC + (t + 1) : GC + ey * P;
+        sR = (ex + 1 < mx) ? np : 1;
+        pT = (ey + 1 < my) ? VR + (t + mx) : GR + ex * P;
+        sT = (ey + 1 < my) ? np : 1;
+        pL = (ex > 0) ? SX + (t - 1) : ZR;
+        sL = (ex > 0) ? np : 0;
+        pB = (ey > 0) ? SY + (t - mx) : ZR;
+        sB = (ey > 0) ? np : 0;
         Real* SINK = lds + L.sink;
-        wVC = hasP ? VC + tid * P : SINK;
-        wVR = hasP ? VR + tid * P : SINK;
-        wSX = hasP ? SX + tid * P : SINK;
-        wSY = hasP ? SY + tid * P : SINK;
+        wVC = hasP ? VC + tid : SINK;
+        wVR = hasP ? VR + tid : SINK;
+        wSX = hasP ? SX + tid : SINK;
+        wSY = hasP ? SY + tid : SINK;
+        sW = hasP ? np : 0;
         const int mxP = mx * P, myP = my * P;
         hasE = tid < mxP + myP + 1;
         e_col = tid <= myP;
@@ -358,14 +369,14 @@ struct PatchCtx {
             e_pub = GC + ek;
             e_line = GC + ek;
             const int eyk = ek / P;
-            e_perp = e_corner ? CORN : SX + (eyk * mx + (mx - 1)) * P + (ek - eyk * P);
+            e_perp = e_corner ? CORN : SX + (ek - eyk * P) * np + (eyk * mx + (mx - 1));
         } else {
             e_il = ek;
             e_jl = myP;
             e_pub = GR + ek;
             e_line = GR + ek;
             const int exk = ek / P;
-            e_perp = SY + ((my - 1) * mx + exk) * P + (ek - exk * P);
+            e_perp = SY + (ek - exk * P) * np + ((my - 1) * mx + exk);
         }
     }
 
@@ -383,9 +394,9 @@ struct PatchCtx {
     // the patch, and the edge node (the corner is stored in both lines).
     __device__ __forceinline__ void publish(const Real (&p)[P][P], Real ep, int mx) {
 #pragma unroll
-        for (int b = 0; b < P; ++b) wVC[b] = p[0][b];
+        for (int b = 0; b < P; ++b) wVC[b * sW] = p[0][b];
 #pragma unroll
-        for (int a = 0; a < P; ++a) wVR[a] = p[a][0];
+        for (int a = 0; a < P; ++a) wVR[a * sW] = p[a][0];
         *e_pub = ep;
         if (e_corner) GR[mx * P] = ep;
     }
@@ -529,9 +540,9 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
             // neighbour term is added last in every sum
             Real pr[P], pt[P], ew[2 * P + 1];
 #pragma unroll
-            for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
+            for (int b = 0; b < P; ++b) pr[b] = C.pR[b * C.sR];
 #pragma unroll
-            for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
+            for (int a = 0; a < P; ++a) pt[a] = C.pT[a * C.sT];
 #pragma unroll
             for (int j = 0; j <= 2 * P; ++j) ew[j] = C.e_line[j - P];
             Real X[P][P], Y[P][P], sx[P], sy[P];
@@ -560,9 +571,9 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
                 }
             // partial sums owed to the right / top neighbours' vertex lines
 #pragma unroll
-            for (int b = 0; b < P; ++b) C.wSX[b] = fma(C.K(P, P), pr[b], sx[b]);
+            for (int b = 0; b < P; ++b) C.wSX[b * C.sW] = fma(C.K(P, P), pr[b], sx[b]);
 #pragma unroll
-            for (int a = 0; a < P; ++a) C.wSY[a] = fma(C.K(P, P), pt[a], sy[a]);
+            for (int a = 0; a < P; ++a) C.wSY[a * C.sW] = fma(C.K(P, P), pt[a], sy[a]);
             Real eL = Real(0);
 #pragma unroll
             for (int j = 0; j <= 2 * P; ++j) eL = fma(C.ew[j], ew[j], eL);
@@ -589,9 +600,9 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
             {
                 Real pl[P], pbm[P];
 #pragma unroll
-                for (int b = 0; b < P; ++b) pl[b] = C.pL[b];
+                for (int b = 0; b < P; ++b) pl[b] = C.pL[b * C.sL];
 #pragma unroll
-                for (int a = 0; a < P; ++a) pbm[a] = C.pB[a];
+                for (int a = 0; a < P; ++a) pbm[a] = C.pB[a * C.sB];
                 const Real eP = *C.e_perp;
                 // interior slots: filter sum of the new velocity
 #pragma unroll
@@ -693,13 +704,13 @@ __global__ void __launch_bounds__(WG) apply_patch_kernel(const SweepArgs<Real> A
     if (C.hasP) {
         Real pr[P], pt[P];
 #pragma unroll
-        for (int b = 0; b < P; ++b) pr[b] = C.pR[b];
+        for (int b = 0; b < P; ++b) pr[b] = C.pR[b * C.sR];
 #pragma unroll
-        for (int a = 0; a < P; ++a) pt[a] = C.pT[a];
+        for (int a = 0; a < P; ++a) pt[a] = C.pT[a * C.sT];
 #pragma unroll
-        for (int b = 0; b < P; ++b) C.SX[threadIdx.x * P + b] = C.xsum(p, P, b, pr[b]);
+        for (int b = 0; b < P; ++b) C.wSX[b * C.sW] = C.xsum(p, P, b, pr[b]);
 #pragma unroll
-        for (int a = 0; a < P; ++a) C.SY[threadIdx.x * P + a] = C.ysum(p, a, P, pt[a]);
+        for (int a = 0; a < P; ++a) C.wSY[a * C.sW] = C.ysum(p, a, P, pt[a]);
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
@@ -715,9 +726,9 @@ __global__ void __launch_bounds__(WG) apply_patch_kernel(const SweepArgs<Real> A
     const double* wy = wx + d.nxl;
     if (C.hasP) {
 #pragma unroll
-        for (int b = 0; b < P; ++b) X[0][b] += C.pL[b];
+        for (int b = 0; b < P; ++b) X[0][b] += C.pL[b * C.sL];
 #pragma unroll
-        for (int a = 0; a < P; ++a) Y[a][0] += C.pB[a];
+        for (int a = 0; a < P; ++a) Y[a][0] += C.pB[a * C.sB];
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll

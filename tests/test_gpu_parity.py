@@ -142,6 +142,34 @@ def test_sweep_converged_matches_lu(gpu_lib, layout):
     assert _rel([g_gpu], [g_ref]) < 1e-9
 
 
+@pytest.mark.parametrize("layout", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_full_workgroup_subdomains(gpu_lib, layout, prec):
+    """Subdomains of 16x16 elements at P = 3 (2401 nodes, the shape of the
+    256x256 waveguide's subdomains): all 256 threads of the patch layouts
+    own an element and 97 of them an edge node.  A 2x2 grid of them, a
+    source, random interface data, exactly 2 WaveHoltz iterations against
+    the oracle's WaveHoltz."""
+    W = gpu_lib
+    nx, ny, P, sx, sy = 32, 32, 3, 2, 2
+    om, m = 60.0, 2
+    h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, precision=prec, layout=layout,
+                       tau_in=0.0, max_wh=m)
+    assert W.dd_layout(h) == (layout, 256)
+    dec, X, Y = _oracle(nx, ny, P, sx, sy, om, _cwave)
+    print(f"sweep 16x16-element subdomains layout={layout} prec={prec}", flush=True)
+    g = _random_g(dec, 17)
+    f = np.exp(-((X - 0.45) ** 2 + (Y - 0.6) ** 2) / 0.01)
+    fl = np.exp(-((Xl - 0.45) ** 2 + (Yl - 0.6) ** 2) / 0.01)
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, fl, 1.0)
+    W.dd_destroy(h)
+    g_ref, u_ref = dec.sweep(g, f, 1.0, wh.make_solver(dec, fixed_iters=m))
+    assert (its == m).all()
+    tol = 1e-11 if prec == 0 else 1e-4
+    assert _rel([u_gpu], u_ref) < tol
+    assert _rel([g_gpu], [g_ref]) < tol
+
+
 def test_autotuned_layout_is_a_fitting_layout(gpu_lib):
     W = gpu_lib
     h, _, _ = _setup(W, 8, 8, 2, 2, 2, 10.0, _cwave)  # auto
