@@ -327,6 +327,54 @@ def test_solve_c1_fp32_refined(gpu_lib, layout):
     assert err < 1e-6
 
 
+def _c2_small_pair(W, **opt):
+    import workloads
+    wl = workloads.c2_small()
+    h, Xl, Yl = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, **opt)
+    dec, X, Y = _oracle(wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c)
+    return wl, h, Xl, Yl, dec, X, Y
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_c2_small_matches_oracle_dd(gpu_lib, prec):
+    """The waveguide at 64x64 elements with the benchmark's subdomain shape
+    (4x4 subdomains of 16x16 elements, P = 3): the full GMRES solve against
+    the oracle DD (splu subdomain solves, same GMRES) at the same outer
+    tolerance.  FP64 with tau_in = 1e-12: 1e-10 and the same iteration count;
+    FP32 sweeps (tau_in = 1e-5) with FP64 refinement: 1e-6.  The WaveHoltz
+    cap is 1000: the waveguide-junction subdomains need up to ~160 periods
+    to reach 1e-12 (the default cap of 100 stops them near 1e-8)."""
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c2_small_pair(W, precision=prec, max_wh=1000,
+                                              tau_in=1e-12 if prec == 0 else 1e-5)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, max_iter=2000)
+    W.dd_destroy(h)
+    us_ref, info = dd.solve_dd(dec, wl.f(X, Y), tol=wl.tol)
+    err = _rel([u], [dec.glue(us_ref)])
+    print(f"c2_small prec={prec} gpu iters={st['outer_iters']} oracle iters={info['iters']} "
+          f"wh_max={st['wh_iters_max']} err={err:.2e}", flush=True)
+    assert st["true_rel_residual"] <= wl.tol
+    if prec == 0:
+        assert st["outer_iters"] == info["iters"]
+        assert err < 1e-10
+    else:
+        assert err < 1e-6
+
+
+def test_solve_c2_small_default_cap(gpu_lib):
+    """At the default WaveHoltz cap (100) the junction subdomains stop
+    before tau_in = 1e-12; the solve still meets the outer tolerance and
+    stays within 1e-6 of the oracle DD."""
+    W = gpu_lib
+    wl, h, Xl, Yl, dec, X, Y = _c2_small_pair(W, tau_in=1e-12)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, max_iter=2000)
+    W.dd_destroy(h)
+    us_ref, _ = dd.solve_dd(dec, wl.f(X, Y), tol=wl.tol)
+    assert st["wh_iters_max"] == 100
+    assert st["true_rel_residual"] <= wl.tol
+    assert _rel([u], [dec.glue(us_ref)]) < 1e-6
+
+
 def test_solve_c1_fp32_plain(gpu_lib):
     """FP32 sweeps and FP32-accurate outer residuals only: the error floor is
     the FP32 operator's (reported, bounded loosely)."""
