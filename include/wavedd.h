@@ -361,8 +361,9 @@ int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stat
                    double* times);
 
 /* Block until some submitted, not yet collected request is done; *id
- * receives it (collect it with dd_engine_wait).  DD_EINVAL if none is
- * outstanding. */
+ * receives it (collect it with dd_engine_wait).  Each request is returned
+ * once.  DD_EINVAL if no outstanding request remains that this call has
+ * not already returned. */
 int dd_engine_wait_any(dd_engine* e, int64_t* id);
 
 int dd_engine_get_info(dd_engine* e, dd_engine_info* info);

@@ -2547,7 +2547,9 @@ int dd_engine_wait(dd_engine* e, int64_t id, double* u_re, double* u_im, dd_stat
 int dd_engine_wait_any(dd_engine* e, int64_t* id) {
     if (!e || !id) return fail(DD_EINVAL, "null argument");
     std::unique_lock<std::mutex> lk(e->mu);
-    if (e->reqs.empty()) return fail(DD_EINVAL, "no outstanding request");
+    bool unclaimed = false;
+    for (auto& kv : e->reqs) unclaimed = unclaimed || !kv.second->claimed;
+    if (!unclaimed) return fail(DD_EINVAL, "no outstanding request that wait_any has not returned");
     int64_t found = -1;
     e->cv.wait(lk, [&] {
         for (auto& kv : e->reqs)

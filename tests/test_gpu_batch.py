@@ -161,6 +161,27 @@ def test_engine_mix_matches_alone_and_single(gpu_lib):
         assert times[0] <= times[1] <= times[2]
 
 
+def test_engine_wait_any_returns_each_request_once(gpu_lib):
+    """wait_any hands out every finished request once; with none left that
+    it has not returned (or none outstanding) it fails instead of blocking."""
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(2)]
+    e = W.dd_engine_create(1 << 30, 2, W.dd_default_options(tau_in=1e-10))
+    try:
+        ids = [W.dd_engine_submit(e, specs[k], specs[k]["f"], 1e-8) for k in (0, 1)]
+        got = sorted(W.dd_engine_wait_any(e) for _ in ids)
+        assert got == sorted(ids)
+        with pytest.raises(W.WaveddError):
+            W.dd_engine_wait_any(e)
+        for rid, k in zip(ids, (0, 1)):
+            *_, rc = W.dd_engine_wait(e, rid, specs[k]["c"].size)
+            assert rc == W.DD_OK
+        with pytest.raises(W.WaveddError):
+            W.dd_engine_wait_any(e)
+    finally:
+        W.dd_engine_destroy(e)
+
+
 def test_engine_admission_under_a_small_budget(gpu_lib):
     """A 64 MiB engine admits requests as memory frees up and rejects one
     larger than all it holds."""
