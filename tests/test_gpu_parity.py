@@ -47,7 +47,8 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-SHAPES = [(6, 4, 3, 2, 2), (8, 8, 2, 2, 2), (4, 6, 1, 2, 3), (4, 4, 4, 2, 1), (3, 5, 3, 1, 1)]
+SHAPES = [(6, 4, 3, 2, 2), (8, 8, 2, 2, 2), (4, 6, 1, 2, 3), (4, 4, 4, 2, 1), (3, 5, 3, 1, 1),
+          (4, 3, 3, 4, 3)]  # last: one element per subdomain
 LAYOUTS = [1, 2, 3, 4]  # DD_LAYOUT_NODE, _PATCH, _PATCH_XCHG, _STREAM
 
 
@@ -373,6 +374,18 @@ def test_solve_c2_small_default_cap(gpu_lib):
     assert st["wh_iters_max"] == 100
     assert st["true_rel_residual"] <= wl.tol
     assert _rel([u], [dec.glue(us_ref)]) < 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_zero_data_gives_zero(gpu_lib, prec):
+    """No source and no boundary data: the solution is exactly zero, found
+    without an outer iteration."""
+    W = gpu_lib
+    h, Xl, Yl = _setup(W, 6, 4, 3, 2, 2, 9.0, _cwave, precision=prec)
+    u, st, rc = W.dd_solve(h, None, None, 1e-8)
+    W.dd_destroy(h)
+    assert rc == W.DD_OK and st["outer_iters"] == 0
+    assert not np.any(u)
 
 
 def test_solve_c1_fp32_plain(gpu_lib):
