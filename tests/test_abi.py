@@ -147,3 +147,38 @@ def test_no_device_is_reported():
     with pytest.raises(wavedd.WaveddError) as ei:
         wavedd.dd_engine_create(1 << 30, 4)
     assert ei.value.code == wavedd.DD_ENODEV
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the size and field offsets the C
+    compiler gives the header's structs (a tiny C program built with gcc
+    against include/wavedd.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {name: getattr(wavedd, name) for name in
+               ("dd_mesh", "dd_partition", "dd_options", "dd_stats", "dd_problem",
+                "dd_engine_info")}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wavedd.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
