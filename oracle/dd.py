@@ -23,6 +23,34 @@ side s of l facing side s' of r,
 consistency condition (d_{n_l} - ik)u + (d_{n_r} - ik)u = -2iku forces -2ik.)
 Physical slots of the output are zero.
 
+Second-order transmission condition (optional, q > 0).  The paper takes the
+zeroth-order condition for simplicity and names optimized / higher-order
+conditions as the natural replacement (Sec. III and the conclusion).  Reading
+taken here: on interface sides
+    B = d_n - i k - q (d_tt + k^2),   q >= 0 a real length,
+i.e. the second-order term of the Taylor expansion of the transparent
+condition with a real coefficient, so that it stays local in time.  Its weak
+form adds q <d_t u, d_t phi> - q k^2 <u, phi> on the side: a 1D stiffness and
+a 1D mass along the side.  They are lumped so that the subdomain operator
+keeps its Kronecker form with the side's lumped 1D weights extended by q at
+every interface end:
+    Wx' = Wx + q (e_first [left is an interface] + e_last [right is one]),
+    A' = Kx (x) Wy' + Wx' (x) Ky,   M' = Wx' (x) Wy' / c^2,
+(H, the source weights and the weights of g in b stay unextended).  This is
+the side terms q (K_side - omega^2 W_side / c^2) plus q^2 / c^2 at a corner
+where two interface sides meet, which the update splits evenly between the
+two sides:
+    g_{r,s'} <- -g_{l,s} - 2 i (omega/c) u_l
+                + 2 (q K_side u_l - omega^2 m u_l / c^2) / W_side,
+    m = q W_side (+ q^2/2 at an end whose other side is an interface).
+Summed over the subdomains that share a node, the extra terms cancel against
+the interface data, so the fixed point is still the global solution.  Since
+Wx' >= Wx, lambda_max(M'^-1 A') obeys the same time-step bound.  For a
+Fourier mode e^{i xi t} along a straight interface the two-subdomain
+convergence factor is |(s - lam)/(s + lam)|^2, s = -ik + q (xi^2 - k^2),
+lam = sqrt(xi^2 - k^2): below 1 for evanescent modes (xi > k) when q > 0,
+where the zeroth-order condition (q = 0) leaves it at exactly 1.
+
 Outer iteration (Sec. III, last paragraph): the sweep is affine,
 G' = T G + h with h = sweep(g_phys, src=1) and T G = sweep(G, src=0); the
 fixed point solves (I - T) G = h.  The Krylov method is not named in the
@@ -50,10 +78,12 @@ class Partition:
 class Decomposition:
     """Geometry and per-subdomain systems of a uniform block partition."""
 
-    def __init__(self, mesh, part, c, omega):
+    def __init__(self, mesh, part, c, omega, q=0.0):
         if mesh.nx % part.sx or mesh.ny % part.sy:
             raise ValueError("partition must divide the element grid")
-        self.mesh, self.part, self.omega = mesh, part, float(omega)
+        if not q >= 0.0:
+            raise ValueError("q must be >= 0")
+        self.mesh, self.part, self.omega, self.q = mesh, part, float(omega), float(q)
         self.c = np.asarray(c, dtype=float)
         self.mx, self.my = mesh.nx // part.sx, mesh.ny // part.sy
         P = mesh.P
@@ -105,9 +135,20 @@ class Decomposition:
         cl = self.c[self.global_nodes(l)]
         M = area / cl ** 2
         H = sem.boundary_diag(self.nxl, self.nyl, Wx, Wy, cl)
-        S = (A - 1j * self.omega * sp.diags(H) - self.omega ** 2 * sp.diags(M)).tocsc()
-        return dict(rect=rect, A=A, M=M, H=H, area=area, c=cl,
-                    side_w=sem.side_weights(Wx, Wy), S=S, lu=None)
+        Kx, _ = sem.assemble_1d(rect.nx, rect.P, rect.hx)
+        Ky, _ = sem.assemble_1d(rect.ny, rect.P, rect.hy)
+        iface = [self.neighbour(l, s) is not None for s in range(4)]
+        # second-order transmission terms: 1D weights extended at interface ends
+        Wxt, Wyt = Wx.copy(), Wy.copy()
+        Wxt[0] += self.q * iface[LEFT]
+        Wxt[-1] += self.q * iface[RIGHT]
+        Wyt[0] += self.q * iface[BOTTOM]
+        Wyt[-1] += self.q * iface[TOP]
+        At = (sp.kron(sp.diags(Wyt), Kx) + sp.kron(Ky, sp.diags(Wxt))).tocsr()
+        Mt = np.kron(Wyt, Wxt) / cl ** 2
+        S = (At - 1j * self.omega * sp.diags(H) - self.omega ** 2 * sp.diags(Mt)).tocsc()
+        return dict(rect=rect, A=A, M=M, At=At, Mt=Mt, H=H, area=area, c=cl, iface=iface,
+                    side_w=sem.side_weights(Wx, Wy), side_K=[Ky, Ky, Kx, Kx], S=S, lu=None)
 
     def lu(self, l):
         sd = self.subs[l]
@@ -155,16 +196,27 @@ class Decomposition:
         return b
 
     def exchange(self, l, u, g_in, g_out):
-        """Write -g_{l,s} - 2 i (omega/c) u_l into each neighbour's slot."""
+        """Write -g_{l,s} - 2 i (omega/c) u_l (+ the second-order terms) into
+        each neighbour's slot."""
         sd = self.subs[l]
+        # the sides meeting side s at its first / last node
+        ends = {LEFT: (BOTTOM, TOP), RIGHT: (BOTTOM, TOP), BOTTOM: (LEFT, RIGHT), TOP: (LEFT, RIGHT)}
         for s in range(4):
             nb = self.neighbour(l, s)
             if nb is None:
                 continue
             r, s2 = nb
             nodes = self.local_sides[s]
-            g_out[self.slot(r, s2)] = (-g_in[self.slot(l, s)]
-                                       - 2j * (self.omega / sd["c"][nodes]) * u[nodes])
+            c = sd["c"][nodes]
+            g = -g_in[self.slot(l, s)] - 2j * (self.omega / c) * u[nodes]
+            if self.q > 0.0:
+                W = sd["side_w"][s]
+                m = self.q * W
+                m[0] += 0.5 * self.q ** 2 * sd["iface"][ends[s][0]]
+                m[-1] += 0.5 * self.q ** 2 * sd["iface"][ends[s][1]]
+                g = g + 2.0 * (self.q * (sd["side_K"][s] @ u[nodes])
+                               - self.omega ** 2 * m * u[nodes] / c ** 2) / W
+            g_out[self.slot(r, s2)] = g
 
     # ---- sweeps -------------------------------------------------------------
     def sweep(self, g_in, f, src, solver=None):

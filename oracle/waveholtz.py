@@ -142,7 +142,7 @@ def make_solver(dec, tol=1e-12, max_iter=100, fixed_iters=None, safety=0.9, coun
 
     def solver(l, b):
         sd = dec.subs[l]
-        u, it = solve(sd["A"], sd["M"], sd["H"], b, dec.omega, nts[l], tol, max_iter, fixed_iters)
+        u, it = solve(sd["At"], sd["Mt"], sd["H"], b, dec.omega, nts[l], tol, max_iter, fixed_iters)
         if counts is not None:
             counts.append(it)
         return u
