@@ -112,6 +112,15 @@ typedef struct {
                         previous sweep's subdomain solutions.  Krylov matvec inputs are
                         unrelated from one matvec to the next, so GMRES ignores it.
                         0 = every WaveHoltz solve starts from u = 0 (default). */
+    double tc2;      /* >= 0: second-order transmission condition on interface sides
+                        (Sec. III names higher-order / optimized conditions as the
+                        replacement of the zeroth-order one): B = d_n - i k - q (d_tt + k^2)
+                        with the real length q = tc2 * min(c) / omega.  Lumped, it extends
+                        each subdomain's 1D weights by q at its interface ends (stiffness
+                        and mass keep their Kronecker form, so the time-step rule is
+                        unchanged) and adds 2 (q K_side u - omega^2 m u / c^2) / W_side to
+                        the interface update; the fixed point stays the global solution.
+                        0 = the paper's zeroth-order condition (default). */
 } dd_options;
 
 typedef struct {
@@ -130,7 +139,7 @@ typedef struct {
 } dd_stats;
 
 /* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
- * no N_t override, cfl 0.9, refine 4, relax 0, warm 0. */
+ * no N_t override, cfl 0.9, refine 4, relax 0, warm 0, tc2 0. */
 int dd_default_options(dd_options* opt);
 
 /* Set up a problem (Sec. II-IV): mesh, degree P in [1, 4], wavespeed c > 0

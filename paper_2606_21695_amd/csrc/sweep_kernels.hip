@@ -176,30 +176,74 @@ __device__ __forceinline__ void slot_finish(const Slot<Real>& s, const SweepArgs
     A.u[s.node] = make_double2(ur, ui);
 }
 
+// (K_side u)(pos) along one side of the subdomain: the assembled 1D
+// stiffness (2/h) sum_e Khat_e of the side's n_el elements (natural ends)
+// applied to the complex iterate u at the side nodes base + j * stride.
+template <typename Real>
+__device__ double2 side_stiffness(const SweepArgs<Real>& A, const double2* u, int64_t base,
+                                  int stride, int pos, int n_el, int P, double scale) {
+    double sx = 0.0, sy = 0.0;
+    const int e0 = pos / P, a0 = pos - e0 * P;
+    // element e0 (local row a0), and element e0 - 1 (local row P) at a vertex
+    for (int side = 0; side < 2; ++side) {
+        const int e = side == 0 ? e0 : e0 - 1;
+        const int a = side == 0 ? a0 : P;
+        if (e < 0 || e >= n_el || (side == 1 && a0 != 0)) continue;
+        for (int q = 0; q <= P; ++q) {
+            const double k = A.K1[P][a][q];
+            const double2 v = u[base + (int64_t)(e * P + q) * stride];
+            sx += k * v.x;
+            sy += k * v.y;
+        }
+    }
+    return make_double2(scale * sx, scale * sy);
+}
+
 // Interface update (eq. (2), sign read for consistency with b):
 // g_{r,s'} = -g_{l,s} - 2 i (omega/c) u_l on each shared side node; outer
-// sides get 0.  Cooperative over the workgroup, coalesced along sides.
+// sides get 0.  With the second-order transmission condition (tc_q = q > 0)
+// it adds 2 (q K_side u - omega^2 m u / c^2) / W_side, m = q W_side plus
+// q^2/2 at an end whose other side is an interface as well.  Cooperative
+// over the workgroup, coalesced along sides.
 template <typename Real>
 __device__ void exchange(const SweepArgs<Real>& A, const SubDesc& d) {
     const int nxl = d.nxl, nyl = d.nyl;
     const int per = 2 * nyl + 2 * nxl;
     for (int k = threadIdx.x; k < per; k += blockDim.x) {
-        int pos, node;
-        int64_t dst;
+        int s, pos, node;
         if (k < nyl) {
-            pos = k; node = k * nxl; dst = d.nbr_off[0];
+            s = 0; pos = k; node = k * nxl;
         } else if (k < 2 * nyl) {
-            pos = k - nyl; node = pos * nxl + nxl - 1; dst = d.nbr_off[1];
+            s = 1; pos = k - nyl; node = pos * nxl + nxl - 1;
         } else if (k < 2 * nyl + nxl) {
-            pos = k - 2 * nyl; node = pos; dst = d.nbr_off[2];
+            s = 2; pos = k - 2 * nyl; node = pos;
         } else {
-            pos = k - 2 * nyl - nxl; node = (nyl - 1) * nxl + pos; dst = d.nbr_off[3];
+            s = 3; pos = k - 2 * nyl - nxl; node = (nyl - 1) * nxl + pos;
         }
+        const int64_t dst = d.nbr_off[s];
         if (dst >= 0) {
             const double2 g = A.g_in[d.if_off + k];
             const double K = A.kside[d.if_off + k];
             const double2 u = A.u[d.node_off + node];
-            A.g_out[dst + pos] = make_double2(-g.x + 2.0 * K * u.y, -g.y - 2.0 * K * u.x);
+            double gx = -g.x + 2.0 * K * u.y, gy = -g.y - 2.0 * K * u.x;
+            if (d.tc_q > 0.0) {
+                const double q = d.tc_q;
+                const bool vert = s < 2;   // left / right sides run along y
+                const int n = vert ? nyl : nxl;
+                const double W = A.w1d[d.w_off + (vert ? nxl + pos : pos)];
+                double m = q * W;
+                // the sides meeting this one at its first / last node
+                if (pos == 0 && d.nbr_off[vert ? 2 : 0] >= 0) m += 0.5 * q * q;
+                if (pos == n - 1 && d.nbr_off[vert ? 3 : 1] >= 0) m += 0.5 * q * q;
+                const int64_t base = d.node_off + (vert ? (s == 0 ? 0 : nxl - 1) : (s == 2 ? 0 : (int64_t)(nyl - 1) * nxl));
+                const double2 Ku = side_stiffness(A, A.u, base, vert ? nxl : 1, pos,
+                                                  vert ? d.my : d.mx, d.P,
+                                                  vert ? d.sy_ref : d.sx_ref);
+                const double f = 2.0 / W;
+                gx += f * (q * Ku.x - K * K * m * u.x);
+                gy += f * (q * Ku.y - K * K * m * u.y);
+            }
+            A.g_out[dst + pos] = make_double2(gx, gy);
         } else {
             A.g_out[d.if_off + k] = make_double2(0.0, 0.0);
         }

@@ -1148,6 +1148,7 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
     if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
     if (!(o.relax >= 0.0) || !std::isfinite(o.relax)) return fail(DD_EINVAL, "relax must be >= 0");
     if (o.warm != 0 && o.warm != 1) return fail(DD_EINVAL, "warm must be 0 or 1");
+    if (!(o.tc2 >= 0.0) || !std::isfinite(o.tc2)) return fail(DD_EINVAL, "tc2 must be >= 0");
     const int P = degree;
     const int Nx = mesh->nx * P + 1, Ny = mesh->ny * P + 1;
     const int64_t N = (int64_t)Nx * Ny;
@@ -1249,19 +1250,26 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
     std::vector<double> alpha(nn), betaX(nn), betaY(nn), beta(nn), area(nn);
     std::vector<int> gidx(nn);
     h->desc.resize(L);
+    // second-order transmission condition: q = tc2 * min(c) / omega
+    const double q = o.tc2 > 0.0 ? o.tc2 * *std::min_element(wavespeed, wavespeed + N) / omega : 0.0;
     for (int64_t l = 0; l < L; ++l) {
         const int a = (int)(l % part->sx), b = (int)(l / part->sx);
         const int n = h->nt[l];
         const double half = M_PI / n;  // omega dt / 2
         const double theta = std::tan(half) / omega;
         const double sigma = std::sin(half) / (0.5 * omega);
+        // interface sides (left, right, bottom, top): their ends extend the
+        // 1D weights of stiffness and mass by q (Kronecker form kept)
+        const bool itf[4] = {a > 0, a + 1 < part->sx, b > 0, b + 1 < part->sy};
         for (int jl = 0; jl < nyl; ++jl)
             for (int il = 0; il < nxl; ++il) {
                 const int64_t k = l * nloc + (int64_t)jl * nxl + il;
                 const int64_t gi = (int64_t)(b * my * P + jl) * Nx + a * mx * P + il;
                 const double cc = wavespeed[gi];
                 const double wx = w1d[il], wy = w1d[nxl + jl];
-                const double M = wx * wy / (cc * cc);
+                const double wxt = wx + ((il == 0 && itf[0]) || (il == nxl - 1 && itf[1]) ? q : 0.0);
+                const double wyt = wy + ((jl == 0 && itf[2]) || (jl == nyl - 1 && itf[3]) ? q : 0.0);
+                const double M = wxt * wyt / (cc * cc);
                 double Hs = 0.0;
                 if (il == 0) Hs += wy;
                 if (il == nxl - 1) Hs += wy;
@@ -1270,8 +1278,8 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
                 const double H = Hs / cc;
                 alpha[k] = (M - theta * H) / (M + theta * H);
                 beta[k] = sigma / (M + theta * H);
-                betaX[k] = beta[k] * (2.0 / h->hx) * wy;
-                betaY[k] = beta[k] * (2.0 / h->hy) * wx;
+                betaX[k] = beta[k] * (2.0 / h->hx) * wyt;
+                betaY[k] = beta[k] * (2.0 / h->hy) * wxt;
                 area[k] = wx * wy;
                 gidx[k] = (int)gi;
             }
@@ -1303,6 +1311,7 @@ int prepare(dd_handle* h, const dd_mesh* mesh, int degree, const double* wavespe
         d.sx_ref = 2.0 / h->hx;
         d.sy_ref = 2.0 / h->hy;
         d.ws_off = l * 2 * wdd::stream_pad_nodes(nxl, nyl);
+        d.tc_q = q;
     }
     // interface bookkeeping: omega/c per slot, outer-trace index of physical
     // slots, interface flags
@@ -1658,6 +1667,7 @@ int dd_default_options(dd_options* o) {
     o->refine = 4;
     o->relax = 0.0;
     o->warm = 0;
+    o->tc2 = 0.0;
     return DD_OK;
 }
 

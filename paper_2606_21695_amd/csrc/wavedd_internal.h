@@ -32,6 +32,7 @@ struct SubDesc {
     double tau;          // see max_wh
     int flags;           // bit 0: warm start (first WaveHoltz iteration from the current u)
     int pad1;
+    double tc_q;         // > 0: length q of the second-order transmission condition
 };
 
 // Per-node coefficient arrays of a sweep in the sweep precision `Real`.

@@ -48,7 +48,7 @@ class dd_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("layout", C.c_int), ("tau_in", C.c_double),
                 ("max_wh", C.c_int), ("outer", C.c_int), ("restart", C.c_int),
                 ("nt_override", C.c_int), ("cfl", C.c_double), ("refine", C.c_int),
-                ("relax", C.c_double), ("warm", C.c_int)]
+                ("relax", C.c_double), ("warm", C.c_int), ("tc2", C.c_double)]
 
 
 class dd_stats(C.Structure):

@@ -126,6 +126,37 @@ def test_sweep_fixed_iterations(gpu_lib, shape, layout, prec):
     assert _rel([g_gpu], [g_ref]) < tol
 
 
+@pytest.mark.parametrize("shape", [(6, 4, 3, 2, 2), (6, 6, 2, 3, 2), (4, 3, 3, 4, 3)])
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_second_order_condition(gpu_lib, shape, layout, prec):
+    """Second-order transmission condition (tc2 > 0): one DD cycle of exactly
+    m WaveHoltz iterations against the oracle's sweep with the same
+    q = tc2 * min(c) / omega (extended 1D weights in the coefficients, the
+    tangential terms in the interface update)."""
+    W = gpu_lib
+    nx, ny, P, sx, sy = shape
+    om, m, tc2 = 9.0, 3, 0.3
+    h, Xl, Yl = _setup(W, nx, ny, P, sx, sy, om, _cwave, precision=prec, layout=layout,
+                       tau_in=0.0, max_wh=m, tc2=tc2)
+    mesh = sem.Rect(nx, ny, P)
+    X, Y = sem.node_coords(mesh)
+    q = tc2 * _cwave(Xl, Yl).min() / om
+    dec = dd.Decomposition(mesh, dd.Partition(sx, sy), _cwave(X, Y), om, q=q)
+    print(f"sweep tc2 shape={shape} layout={layout} prec={prec}", flush=True)
+    g = _random_g(dec, sum(shape) + 1)
+    f = np.exp(-((X - 0.4) ** 2 + (Y - 0.55) ** 2) / 0.02)
+    fl = np.exp(-((Xl - 0.4) ** 2 + (Yl - 0.55) ** 2) / 0.02)
+    nt = W.dd_time_steps(h)
+    g_gpu, u_gpu, its = W.dd_sweep(h, g, fl, 1.0)
+    W.dd_destroy(h)
+    assert list(nt) == wh.subdomain_steps(dec)
+    g_ref, u_ref = dec.sweep(g, f, 1.0, wh.make_solver(dec, fixed_iters=m))
+    tol = 1e-11 if prec == 0 else 1e-4
+    assert _rel([u_gpu], u_ref) < tol
+    assert _rel([g_gpu], [g_ref]) < tol
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_sweep_converged_matches_lu(gpu_lib, layout):
     W = gpu_lib
@@ -386,6 +417,54 @@ def test_solve_zero_data_gives_zero(gpu_lib, prec):
     W.dd_destroy(h)
     assert rc == W.DD_OK and st["outer_iters"] == 0
     assert not np.any(u)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_second_order_condition_matches_oracle_dd(gpu_lib, prec):
+    """c1 with the second-order condition (tc2 = 0.25): FP64 against the oracle
+    DD with the same q (1e-10, same iteration count), FP32 sweeps with FP64
+    refinement against the global solution (1e-6); fewer outer iterations
+    than the zeroth-order condition."""
+    W = gpu_lib
+    tc2 = 0.25
+    tau = 1e-12 if prec == 0 else 1e-6
+    wl, h, Xl, Yl, dec0, X, Y = _c1_pair(W, precision=prec, tau_in=tau, tc2=tc2)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol)
+    W.dd_destroy(h)
+    h0, _, _ = _setup(W, wl.nx, wl.ny, wl.P, wl.sx, wl.sy, wl.omega, wl.c, precision=prec,
+                      tau_in=tau)
+    _, st0, _ = W.dd_solve(h0, wl.f(Xl, Yl), None, wl.tol)
+    W.dd_destroy(h0)
+    q = tc2 * wl.c(Xl, Yl).min() / wl.omega
+    dec = dd.Decomposition(dec0.mesh, dec0.part, wl.c(X, Y), wl.omega, q=q)
+    us_ref, info = dd.solve_dd(dec, wl.f(X, Y), tol=wl.tol)
+    print(f"c1 tc2 prec={prec} gpu iters={st['outer_iters']} oracle iters={info['iters']} "
+          f"zeroth-order iters={st0['outer_iters']}", flush=True)
+    assert st["true_rel_residual"] <= wl.tol
+    assert st["outer_iters"] < st0["outer_iters"]
+    if prec == 0:
+        assert st["outer_iters"] == info["iters"]
+        assert _rel([u], [dec.glue(us_ref)]) < 1e-10
+    else:
+        u_lu = sem.solve(dec.mesh, wl.c(X, Y), wl.omega, wl.f(X, Y))
+        assert _rel([u], [u_lu]) < 1e-6
+
+
+def test_solve_c2_small_second_order_condition(gpu_lib):
+    """The benchmark's subdomain shape with the second-order condition
+    (tc2 = 0.25, cap 1000): FP64 solve against the oracle DD with the same q."""
+    W = gpu_lib
+    wl, h, Xl, Yl, dec0, X, Y = _c2_small_pair(W, max_wh=1000, tau_in=1e-12, tc2=0.25)
+    u, st, _ = W.dd_solve(h, wl.f(Xl, Yl), None, wl.tol, max_iter=2000)
+    W.dd_destroy(h)
+    q = 0.25 * wl.c(Xl, Yl).min() / wl.omega
+    dec = dd.Decomposition(dec0.mesh, dec0.part, wl.c(X, Y), wl.omega, q=q)
+    us_ref, info = dd.solve_dd(dec, wl.f(X, Y), tol=wl.tol)
+    err = _rel([u], [dec.glue(us_ref)])
+    print(f"c2_small tc2 gpu iters={st['outer_iters']} oracle iters={info['iters']} err={err:.2e}",
+          flush=True)
+    assert st["outer_iters"] == info["iters"]
+    assert err < 1e-10
 
 
 def test_solve_c1_fp32_plain(gpu_lib):
