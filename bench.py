@@ -102,23 +102,27 @@ def cpu_baseline(wl, seconds=12.0):
                       f"one thread ({el:.1f} s; oracle setup {setup_s:.1f} s not counted)"}
 
 
-VARIANTS = {"fp32_refined": ("fp32", 1e-6, 0.0), "fp64_relaxed": ("fp64", None, 0.1),
-            "fp32_refined_relaxed": ("fp32", 1e-6, 0.1)}
+# name: (sweep precision, inner tolerance (None: the workload's), relax, tc2)
+VARIANTS = {"fp32_refined": ("fp32", 1e-6, 0.0, 0.0), "fp64_relaxed": ("fp64", None, 0.1, 0.0),
+            "fp32_refined_relaxed": ("fp32", 1e-6, 0.1, 0.0),
+            "fp64_tc2": ("fp64", None, 0.0, 0.1),
+            "fp32_refined_relaxed_tc2": ("fp32", 1e-6, 0.1, 0.1)}
 
 
 def variants(W, wl, u_ref, names, max_wh, progress=0, steps=2):
-    """FP32 sweeps (with FP64 refinement) and relaxed inner tolerance on the
-    same workload: solves/s, latency, DOF-updates/s and the relative L2
-    difference from the main run's solution."""
+    """FP32 sweeps (with FP64 refinement), relaxed inner tolerance and the
+    second-order transmission condition on the same workload: solves/s,
+    latency, DOF-updates/s and the relative L2 difference from the main
+    run's solution."""
     import torch
     out = {}
     N = u_ref.size
     dev = torch.device("cuda:0")
     for name in names:
-        pname, tau, relax = VARIANTS[name]
+        pname, tau, relax, tc2 = VARIANTS[name]
         prec = W.DD_FP64 if pname == "fp64" else W.DD_FP32
         tau = wl.tau_in if tau is None else tau
-        prob = W.Problem(wl, precision=prec, tau_in=tau, relax=relax, max_wh=max_wh)
+        prob = W.Problem(wl, precision=prec, tau_in=tau, relax=relax, max_wh=max_wh, tc2=tc2)
         if progress:
             W.dd_set_progress(prob.h, lambda it, rel, n=name: log(f"  {n} outer {it}: {rel:.2e}"),
                               progress)
@@ -145,7 +149,7 @@ def variants(W, wl, u_ref, names, max_wh, progress=0, steps=2):
                      "true_rel_residual_interface": st["true_rel_residual"],
                      "rel_l2_vs_fp64": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
                      "rel_residual_global_fp64": W.dd_residual(prob.h, u, prob.f),
-                     "tau_in": tau, "relax": relax}
+                     "tau_in": tau, "relax": relax, "tc2": tc2}
         prob.close()
     return out
 
@@ -393,7 +397,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
     ap.add_argument("--variants", default=None,
-                    help="comma-separated comparison solves (default: all three for the "
+                    help="comma-separated comparison solves (default: all for the "
                          "256x256 workloads, fp32_refined_relaxed for 512x512)")
     ap.add_argument("--progress", type=int, default=None,
                     help="print the outer residual every N iterations (default: 25 for "
