@@ -32,9 +32,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 # kernel's source (its layout section plus the shared helpers) and the run;
 # reported as null once that source changes.
 MEASURED_TRAFFIC = {
-    ("28534c7ad0307332", "solve", "c2", "fp64"): round((15275.8 * 2.0 + 22263.8) * 1024),
-    ("56d22eeacc7fb5c3", "protocol", "c3", "fp64"): round((57463302.4 * 2.0 + 63327220.4) * 1024),
-    ("56d22eeacc7fb5c3", "protocol", "c3", "fp32"): round((28810021.6 * 2.0 + 31881872.7) * 1024),
+    ("2825823c8f82db8c", "solve", "c2", "fp64"): round((19782.4 * 2.0 + 32432.0) * 1024),
+    ("8413cb69dc6df629", "protocol", "c3", "fp64"): round((57468569.1 * 2.0 + 63332868.5) * 1024),
+    ("8413cb69dc6df629", "protocol", "c3", "fp32"): round((28815929.2 * 2.0 + 31884724.0) * 1024),
 }
 
 # section markers of each layout in the kernel source

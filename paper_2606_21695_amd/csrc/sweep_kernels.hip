@@ -538,22 +538,30 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
     const bool warm = A.warm != 0 || (d.flags & 1) != 0;
     for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
+        // p, pdot from u: read at the first iteration (warm start), after
+        // that still in registers from the end of the previous iteration
 #pragma unroll
         for (int a = 0; a < P; ++a)
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                if ((m > 0 || warm) && C.hasP) {
-                    const double2 u = A.u[base + (int64_t)b * nxl + a];
-                    p[a][b] = (Real)u.x;
-                    pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
-                } else {
+                if (m == 0) {
                     p[a][b] = Real(0);
                     pd[a][b] = Real(0);
+                    if (warm && C.hasP) {
+                        const double2 u = A.u[base + (int64_t)b * nxl + a];
+                        p[a][b] = (Real)u.x;
+                        pd[a][b] = (Real)(u.y * pd0c - u.x * pd0s);
+                    }
                 }
                 vr[a][b] = k0 * p[a][b];
                 vi[a][b] = kh0 * pd[a][b];
             }
-        if (C.hasE) slot_init(e, A, d, m > 0 || warm, k0, kh0);
+        if (m == 0) {
+            if (C.hasE) slot_init(e, A, d, warm, k0, kh0);
+        } else {
+            e.vr = k0 * e.p;
+            e.vi = kh0 * e.pd;
+        }
 
         for (int nu = 1; nu < nt; ++nu) {
             const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
@@ -695,9 +703,17 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
                     dsum += (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
                     nsum += ur * ur + ui * ui;
                     A.u[n] = make_double2(ur, ui);
+                    // start of the next iteration (the values a read of u gives)
+                    p[a][b] = (Real)ur;
+                    pd[a][b] = (Real)(ui * pd0c - ur * pd0s);
                 }
         }
-        if (C.hasE) slot_finish(e, A, d, m > 0 || warm, dsum, nsum);
+        if (C.hasE) {
+            slot_finish(e, A, d, m > 0 || warm, dsum, nsum);
+            const double ur = d.two_over_nt * (double)e.vr, ui = d.two_over_nt * (double)e.vi;
+            e.p = (Real)ur;
+            e.pd = (Real)(ui * pd0c - ur * pd0s);
+        }
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;  // non-finite iterate: stop, reported by the host
