@@ -43,6 +43,7 @@ _SECTIONS = {1: ("// NODE layout (one DOF per thread)", "// STREAM layout"),
              3: ("// PATCH layout\n", "// PATCH layout, one barrier per step"),
              4: ("// STREAM layout", "}  // namespace\n")}
 LAYOUT_NAMES = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}
+LAYOUT_IDS = {"auto": 0, **{v: k for k, v in LAYOUT_NAMES.items()}}
 KERNEL_NAMES = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
                 4: "sweep_stream_kernel"}
 
@@ -349,7 +350,7 @@ def protocol_bench(args):
         traffic = None
     else:
         wl = workloads.CONFIGS[args.config]()
-        prob = W.Problem(wl, precision=prec, tau_in=0.0, max_wh=5)
+        prob = W.Problem(wl, precision=prec, layout=LAYOUT_IDS[args.layout], tau_in=0.0, max_wh=5)
         h = prob.h
         rng = np.random.default_rng(1)
         n = W.dd_sizes(h)["n_iface"]
@@ -389,6 +390,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
+    ap.add_argument("--layout", default="auto", choices=sorted(LAYOUT_IDS),
+                    help="sweep layout (auto = the autotuner's choice)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--relax", type=float, default=0.0,
                     help="variable inner tolerance factor (0 = fixed inner tolerance)")
@@ -435,7 +438,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.max_wh is None:
-        args.max_wh = 100 if args.config in ("c1", "c2", "c2_small") and not args.serve else 1000
+        args.max_wh = 100 if args.config in ("c1", "c2", "c2_small", "c2_t1") and not args.serve else 1000
     if args.serve:
         return serve_bench(args)
     if args.protocol:
@@ -454,7 +457,8 @@ def main():
     if args.tau_in is not None:
         tau = args.tau_in
     t0 = time.perf_counter()
-    prob = W.Problem(wl, precision=prec, tau_in=tau, relax=args.relax, max_wh=args.max_wh)
+    prob = W.Problem(wl, precision=prec, layout=LAYOUT_IDS[args.layout], tau_in=tau,
+                     relax=args.relax, max_wh=args.max_wh)
     setup_s = time.perf_counter() - t0
     if args.progress is None:
         args.progress = 25 if args.config == "c3" else 0

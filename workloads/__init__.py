@@ -16,6 +16,8 @@ follow those shapes:
 * ``c2``  unit square, 256x256 elements, P=3, 16x16 subdomains of 16x16
           elements, Y-waveguide with a slow core c=1/3 in background c=1,
           omega for 10 points per wavelength in the core, off-centre source.
+* ``c2_t1`` the ``c2`` problem on 32x32 subdomains of 8x8 elements (625 nodes,
+          one node per thread fits a workgroup).
 * ``c3``  512x512 elements, P=3, 8x8 subdomains of 64x64 elements, same
           physical problem as ``c2``.
 * ``c4``  a seeded batch of independent problems whose subdomains (8..64
@@ -147,6 +149,14 @@ def c2_small(seed=2):
                     gaussian(0.51, 0.15, 0.01), tol=1e-8, tau_in=1e-12)
 
 
+def c2_t1(seed=2):
+    """The c2 problem partitioned into 32x32 subdomains of 8x8 elements
+    (625 nodes each), small enough for one node per thread."""
+    wl = c2(seed)
+    wl.name, wl.sx, wl.sy = "c2_t1", 32, 32
+    return wl
+
+
 def c3(seed=2):
     om = _omega_ppw(3, 1.0 / 256, 1.0 / 3.0, 10.0)
     return Workload("c3", 512, 512, 3, 8, 8, om, y_waveguide(seed),
@@ -217,4 +227,4 @@ def c5(seed=5, n_requests=2000):
     return reqs
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c2_small": c2_small, "c3": c3}
+CONFIGS = {"c1": c1, "c2": c2, "c2_small": c2_small, "c2_t1": c2_t1, "c3": c3}
