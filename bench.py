@@ -29,12 +29,12 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # a 256 MiB copy: fetch x2.000, write x1.000), keyed by the hash of the
-# kernel's source (its layout section plus the shared helpers) and the run;
-# reported as null once that source changes.
+# kernel's code (its layout section plus the shared helpers, comments
+# ignored) and the run; reported as null once that code changes.
 MEASURED_TRAFFIC = {
-    ("2825823c8f82db8c", "solve", "c2", "fp64"): round((19782.4 * 2.0 + 32432.0) * 1024),
-    ("8413cb69dc6df629", "protocol", "c3", "fp64"): round((57468569.1 * 2.0 + 63332868.5) * 1024),
-    ("8413cb69dc6df629", "protocol", "c3", "fp32"): round((28815929.2 * 2.0 + 31884724.0) * 1024),
+    ("15aca0d8531ab9fe", "solve", "c2", "fp64"): round((19782.4 * 2.0 + 32432.0) * 1024),
+    ("d577db17b639aa2c", "protocol", "c3", "fp64"): round((57468569.1 * 2.0 + 63332868.5) * 1024),
+    ("d577db17b639aa2c", "protocol", "c3", "fp32"): round((28815929.2 * 2.0 + 31884724.0) * 1024),
 }
 
 # section markers of each layout in the kernel source
@@ -48,15 +48,19 @@ KERNEL_NAMES = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patc
                 4: "sweep_stream_kernel"}
 
 
-def kernel_hash(layout):
-    """Hash of the shared device helpers plus the given layout's section."""
+def kernel_hash(layout, src=None):
+    """Hash of the code (comments and blank lines dropped) of the shared
+    device helpers plus the given layout's section."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep_kernels.hip")).read()
+    import re
+    if src is None:
+        src = open(os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep_kernels.hip")).read()
     head = src[:src.index("// PATCH layout\n")]
     a, b = _SECTIONS[layout]
     i = src.index(a)
     body = src[i:src.index(b, i + len(a))]
-    return hashlib.sha256((head + body).encode()).hexdigest()[:16]
+    code = [re.sub(r"//.*$", "", line).rstrip() for line in (head + body).splitlines()]
+    return hashlib.sha256("\n".join(x for x in code if x).encode()).hexdigest()[:16]
 
 
 def log(msg):

@@ -19,9 +19,9 @@
 //    reads its right neighbour's column and top neighbour's row, and exchanges
 //    partial sums for the shared vertex lines (two workgroup barriers per
 //    step).  Interior slots finish between the two barriers.
-//  * PATCH (default): the same ownership with one barrier per step: whole
-//    patches are published (double-buffered) and each thread computes its
-//    left / bottom neighbours' shares of its vertex lines itself.
+//  * PATCH: the same ownership with one barrier per step: whole patches are
+//    published (double-buffered) and each thread computes its left / bottom
+//    neighbours' shares of its vertex lines itself.
 //  * NODE: one thread per node (<= 1024 nodes); p double-buffered in LDS
 //    with zero padding, so the (2P+1)-point 1D windows need no bounds
 //    checks (one barrier per step).
@@ -29,8 +29,9 @@
 //    device memory (zero-padded p grids, one barrier per step); waves walk
 //    up column segments with the Y windows in registers and exchange X
 //    neighbours across lanes.
-// Both stage the per-step filter / forcing tables of the subdomain in LDS
-// (broadcast reads) when the subdomain starts.
+// All stage the per-step filter / forcing tables of the subdomain in LDS
+// (broadcast reads) when the subdomain starts.  The layout of a problem is
+// picked by timing the ones that fit (autotuner in the host library).
 #include "wavedd_internal.h"
 
 namespace wdd {
