@@ -179,7 +179,8 @@ def batch_bench(args):
         tau = args.tau_in
     t0 = time.perf_counter()
     b = W.dd_batch_setup(specs, W.dd_default_options(precision=prec, tau_in=tau,
-                                                     relax=args.relax, max_wh=args.max_wh))
+                                                     relax=args.relax, max_wh=args.max_wh,
+                                                     tc2=args.tc2))
     setup_s = time.perf_counter() - t0
     tol = wls[0].tol
     fs = [s_["f"] for s_ in specs]
@@ -229,7 +230,7 @@ def batch_bench(args):
                                f"{sum(wl.sx * wl.sy for wl in wls)} subdomains, P in 1..4, "
                                f"omega={wls[0].omega}, tol={tol}",
                    "precision": args.precision, "tau_in": tau, "relax": args.relax,
-                   "max_wh": args.max_wh},
+                   "max_wh": args.max_wh, "tc2": args.tc2},
         "problems": len(wls),
         "solves_per_s": len(wls) * args.steps / total,
         "batch_latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
@@ -266,7 +267,7 @@ def serve_bench(args):
     specs = [W.workload_spec(wl) for wl in wls]
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
     o = W.dd_default_options(precision=prec, tau_in=wls[0].tau_in if prec == W.DD_FP32 else 1e-10,
-                             relax=args.relax, max_wh=args.max_wh)
+                             relax=args.relax, max_wh=args.max_wh, tc2=args.tc2)
     budget = int(args.budget_gib * (1 << 30))
 
     def run(arrivals):
@@ -311,7 +312,7 @@ def serve_bench(args):
         "config": {"workload": f"c5: first {len(specs)} requests of <= {args.max_nodes} nodes, "
                                f"Poisson arrivals at rho={args.rho} of saturated throughput",
                    "precision": args.precision, "max_active": args.max_active,
-                   "budget_gib": args.budget_gib},
+                   "budget_gib": args.budget_gib, "tc2": args.tc2},
         "saturated_solves_per_s": mu,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
@@ -400,6 +401,8 @@ def main():
     ap.add_argument("--relax", type=float, default=0.0,
                     help="variable inner tolerance factor (0 = fixed inner tolerance)")
     ap.add_argument("--tau-in", type=float, default=None, help="override the inner tolerance")
+    ap.add_argument("--tc2", type=float, default=0.0,
+                    help="second-order transmission condition (0 = the paper's zeroth order)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
@@ -462,7 +465,7 @@ def main():
         tau = args.tau_in
     t0 = time.perf_counter()
     prob = W.Problem(wl, precision=prec, layout=LAYOUT_IDS[args.layout], tau_in=tau,
-                     relax=args.relax, max_wh=args.max_wh)
+                     relax=args.relax, max_wh=args.max_wh, tc2=args.tc2)
     setup_s = time.perf_counter() - t0
     if args.progress is None:
         args.progress = 25 if args.config == "c3" else 0
@@ -531,7 +534,8 @@ def main():
                                f"{wl.sx}x{wl.sy} subdomains, omega={wl.omega:.2f}, tol={wl.tol}",
                    "precision": args.precision,
                    "layout": LAYOUT_NAMES[lay],
-                   "wg_threads": wg, "tau_in": tau, "relax": args.relax, "max_wh": args.max_wh},
+                   "wg_threads": wg, "tau_in": tau, "relax": args.relax, "max_wh": args.max_wh,
+                   "tc2": args.tc2},
         "solves_per_s": args.steps / total,
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                        "p99": 1e3 * float(np.percentile(lat, 99))},
