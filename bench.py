@@ -431,7 +431,7 @@ def main():
                          "traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the sweep shards by "
+        print(json.dumps({"error": "wavedd runs on one GPU: the sweep shards by "
                                    "subdomain blocks across GPUs by design, but no multi-GPU "
                                    "path is built; use --gpus 1"}))
         sys.exit(2)

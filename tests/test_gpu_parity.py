@@ -9,8 +9,8 @@ Tolerances (relative l2 over the stacked subdomain copies):
   N_t * m * eps_32 * amplification).
 * converged sweep vs sparse LU, FP64: 1e-9 (inner tolerance 1e-12 times the
   WaveHoltz contraction constant).
-* full solve vs the oracle DD at the same outer tolerance: 1e-10 in FP64
-  (spec bar); FP32 subdomain sweeps: 1e-6.
+* full solve vs the oracle DD at the same outer tolerance: 1e-10 in FP64;
+  FP32 subdomain sweeps: 1e-6.
 """
 import numpy as np
 import pytest
