@@ -51,10 +51,13 @@ def _single(W, s, tol, **opt):
     return u, st
 
 
-def test_batch_matches_single_solves(gpu_lib):
+@pytest.mark.parametrize("tc2", [0.0, 0.1])
+def test_batch_matches_single_solves(gpu_lib, tc2):
+    """Batched solves equal single-problem solves bit for bit, with the
+    paper's transmission condition and with the second-order one."""
     W = gpu_lib
     specs = [_spec(W, k) for k in range(len(SPECS))]
-    o = W.dd_default_options(tau_in=1e-12)
+    o = W.dd_default_options(tau_in=1e-12, tc2=tc2)
     b = W.dd_batch_setup(specs, o)
     try:
         lays = [W.dd_layout(W.dd_batch_handle(b, i))[0] for i in range(len(specs))]
@@ -69,7 +72,7 @@ def test_batch_matches_single_solves(gpu_lib):
     # problems' sweeps
     assert max(st["sweeps"] for st in sts) <= launches <= sum(st["sweeps"] for st in sts)
     for i, s in enumerate(specs):
-        u1, st1 = _single(W, s, 1e-8, tau_in=1e-12, layout=lays[i])
+        u1, st1 = _single(W, s, 1e-8, tau_in=1e-12, layout=lays[i], tc2=tc2)
         print(f"problem {i}: batch iters {sts[i]['outer_iters']} single {st1['outer_iters']}",
               flush=True)
         assert sts[i]["outer_iters"] == st1["outer_iters"]
