@@ -328,6 +328,29 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def operator_ms(W, h, reps=50):
+    """Average time of one whole-domain FP64 operator evaluation y = S x
+    (random x), HIP events on the stream the kernel runs on (a stream of its
+    own: a null stream would send the launches to the handle's stream)."""
+    import torch
+    n = W.dd_sizes(h)["n_global"]
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(2 * n, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        W.dd_apply_operator_device(h, x, y, s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        W.dd_apply_operator_device(h, x, y, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def protocol_bench(args):
     """The paper's DD-cycle timing (Sec. VII-A): sweeps of exactly 5
     WaveHoltz iterations per subdomain from random complex interface data,
@@ -361,6 +384,7 @@ def protocol_bench(args):
         n = W.dd_sizes(h)["n_iface"]
         W.dd_set_state(h, rng.standard_normal(n) + 1j * rng.standard_normal(n))
         ms, dof = W.dd_time_sweep(h, args.steps, 5)
+        op_ms = operator_ms(W, h)
         lay, wg = W.dd_layout(h)
         traffic = MEASURED_TRAFFIC.get((kernel_hash(lay), "protocol", args.config, args.precision))
         prob.close()
@@ -376,6 +400,14 @@ def protocol_bench(args):
            "data": "synthetic (random complex interface data)",
            "config": {"workload": desc, "layout": layout, "kernel": kernel},
            "dof_updates_per_launch": dof}
+    if args.config != "c4":
+        # the paper's normaliser (Sec. VII-A): DD-cycle time over the time of one
+        # whole-domain operator evaluation y = S x in FP64
+        out["operator_ms"] = op_ms
+        out["dd_cycle_over_operator"] = ms / op_ms
+        # algorithmic bytes of y = S x per node: x, y (complex) and M, H
+        n_global = (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1)
+        out["operator_gbs"] = 48.0 * n_global / (op_ms * 1e-3) / 1e9
     if flop is not None:
         peak = PEAK_TFLOPS[args.precision]
         ach = flop / (ms * 1e-3) / 1e12
