@@ -178,40 +178,65 @@ __global__ void glue_kernel(const double2* usub, int Nx, int Ny, int P, int mx, 
 
 // y = S x on the global grid: (A x)_{ij} = (2/hx) Wy_j sum_k Khat_x[i,k] x_kj
 // + (2/hy) Wx_i sum_k Khat_y[j,k] x_ik, then - i omega H x - omega^2 M x.
+// One thread per node, blocks of one grid row (no division per thread); the
+// degree is a template parameter so the element windows unroll and the
+// reference matrix entries stay in scalar registers.
+
+// Row a of the reference element matrix, selected with compile-time
+// indices (a is the node's offset inside its element).
+template <int P>
+__device__ __forceinline__ double kref(const double (*K)[kMaxP + 1], int a, int q) {
+    double v = K[0][q];
+#pragma unroll
+    for (int r = 1; r <= P; ++r) v = (a == r) ? K[r][q] : v;
+    return v;
+}
+
+// Assembled 1D stiffness row at node k of a line of n_el elements, applied
+// to x along the line (nodes base + m * step).
+template <int P>
 __device__ __forceinline__ double2 line1d(const double2* x, int64_t base, int64_t step, int k,
-                                          int n_el, int P, const double (*K)[kMaxP + 1]) {
+                                          int n_el, const double (*K)[kMaxP + 1]) {
     const int e = k / P, a = k - e * P;
     double2 s = make_double2(0.0, 0.0);
-    if (a == 0) {
-        if (e < n_el)
-            for (int q = 0; q <= P; ++q) {
-                const double2 v = x[base + (int64_t)(e * P + q) * step];
-                s.x += K[0][q] * v.x;
-                s.y += K[0][q] * v.y;
-            }
-        if (e > 0)
-            for (int q = 0; q <= P; ++q) {
-                const double2 v = x[base + (int64_t)((e - 1) * P + q) * step];
-                s.x += K[P][q] * v.x;
-                s.y += K[P][q] * v.y;
-            }
-    } else {
+    // element e (row a), present unless k is the last node of the line
+    if (e < n_el) {
+#pragma unroll
         for (int q = 0; q <= P; ++q) {
+            const double kv = kref<P>(K, a, q);
             const double2 v = x[base + (int64_t)(e * P + q) * step];
-            s.x += K[a][q] * v.x;
-            s.y += K[a][q] * v.y;
+            s.x += kv * v.x;
+            s.y += kv * v.y;
+        }
+    }
+    // element e - 1 (row P) at a vertex
+    if (a == 0 && e > 0) {
+#pragma unroll
+        for (int q = 0; q <= P; ++q) {
+            const double2 v = x[base + (int64_t)((e - 1) * P + q) * step];
+            s.x += K[P][q] * v.x;
+            s.y += K[P][q] * v.y;
         }
     }
     return s;
 }
 
-__global__ void operator_kernel(const OperatorArgs A, const double2* x, double2* y) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t N = (int64_t)A.Nx * A.Ny;
-    if (g >= N) return;
-    const int i = (int)(g % A.Nx), j = (int)(g / A.Nx);
-    const double2 X = line1d(x, (int64_t)j * A.Nx, 1, i, A.nx, A.P, A.K1);
-    const double2 Y = line1d(x, i, A.Nx, j, A.ny, A.P, A.K1);
+// Node (i, j) of the block's grid row; false past the row's end.
+__device__ __forceinline__ bool grid_node(const OperatorArgs& A, int& i, int& j) {
+    const int bpr = (A.Nx + kBT - 1) / kBT;
+    j = (int)blockIdx.x / bpr;
+    i = ((int)blockIdx.x - j * bpr) * kBT + (int)threadIdx.x;
+    return i < A.Nx;
+}
+
+template <int P>
+__global__ void __launch_bounds__(kBT) operator_kernel(const OperatorArgs A, const double2* x,
+                                                       double2* y) {
+    int i, j;
+    if (!grid_node(A, i, j)) return;
+    const int64_t g = (int64_t)j * A.Nx + i;
+    const double2 X = line1d<P>(x, (int64_t)j * A.Nx, 1, i, A.nx, A.K1);
+    const double2 Y = line1d<P>(x, i, A.Nx, j, A.ny, A.K1);
     const double cx = A.sx_ref * A.wy[j], cy = A.sy_ref * A.wx[i];
     const double2 v = x[g];
     const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
@@ -222,13 +247,15 @@ __global__ void operator_kernel(const OperatorArgs A, const double2* x, double2*
 
 // Per node: r = b - S u with b = (Wx Wy) f + boundary trace terms; writes
 // (|r|^2, |b|^2) for a deterministic reduction.
-__global__ void residual_kernel(const OperatorArgs A, const double2* u, const double* f_re,
-                                const double* f_im, const double* g_re, const double* g_im,
-                                double2* out) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int P>
+__global__ void __launch_bounds__(kBT) residual_kernel(const OperatorArgs A, const double2* u,
+                                                       const double* f_re, const double* f_im,
+                                                       const double* g_re, const double* g_im,
+                                                       double2* out) {
+    int i, j;
+    if (!grid_node(A, i, j)) return;
     const int Nx = A.Nx, Ny = A.Ny;
-    if (g >= (int64_t)Nx * Ny) return;
-    const int i = (int)(g % Nx), j = (int)(g / Nx);
+    const int64_t g = (int64_t)j * Nx + i;
     double br = 0.0, bi = 0.0;
     const double area = A.wx[i] * A.wy[j];
     if (f_re) br = area * f_re[g];
@@ -239,8 +266,8 @@ __global__ void residual_kernel(const OperatorArgs A, const double2* u, const do
     if (i == Nx - 1) { if (g_re) br += A.wy[j] * g_re[tr]; if (g_im) bi += A.wy[j] * g_im[tr]; }
     if (j == 0) { if (g_re) br += A.wx[i] * g_re[tb]; if (g_im) bi += A.wx[i] * g_im[tb]; }
     if (j == Ny - 1) { if (g_re) br += A.wx[i] * g_re[tt]; if (g_im) bi += A.wx[i] * g_im[tt]; }
-    const double2 X = line1d(u, (int64_t)j * Nx, 1, i, A.nx, A.P, A.K1);
-    const double2 Y = line1d(u, i, Nx, j, A.ny, A.P, A.K1);
+    const double2 X = line1d<P>(u, (int64_t)j * Nx, 1, i, A.nx, A.K1);
+    const double2 Y = line1d<P>(u, i, Nx, j, A.ny, A.K1);
     const double cx = A.sx_ref * A.wy[j], cy = A.sy_ref * A.wx[i];
     const double2 v = u[g];
     const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
@@ -266,11 +293,26 @@ inline int nblocks(int64_t n, int bt) { return (int)((n + bt - 1) / bt); }
 
 }  // namespace
 
+// Blocks of the operator / residual launches: whole grid rows of kBT-node
+// blocks.
+static inline unsigned grid_blocks(const OperatorArgs& a) {
+    return (unsigned)(((a.Nx + kBT - 1) / kBT) * (int64_t)a.Ny);
+}
+
 hipError_t launch_residual(const OperatorArgs& a, const double2* u, const double* f_re,
                            const double* f_im, const double* g_re, const double* g_im,
                            double2* work, hipStream_t s) {
-    hipLaunchKernelGGL(residual_kernel, dim3(nblocks((int64_t)a.Nx * a.Ny, kBT)), dim3(kBT), 0, s, a,
-                       u, f_re, f_im, g_re, g_im, work);
+#define L(PP)                                                                                 \
+    hipLaunchKernelGGL((residual_kernel<PP>), dim3(grid_blocks(a)), dim3(kBT), 0, s, a, u, \
+                       f_re, f_im, g_re, g_im, work)
+    switch (a.P) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L
     return hipGetLastError();
 }
 
@@ -370,8 +412,16 @@ hipError_t split_complex(const double2* z, double* re, double* im, int64_t n, hi
 }
 
 hipError_t launch_operator(const OperatorArgs& a, const double2* x, double2* y, hipStream_t s) {
-    hipLaunchKernelGGL(operator_kernel, dim3(nblocks((int64_t)a.Nx * a.Ny, kBT)), dim3(kBT), 0, s, a,
-                       x, y);
+#define L(PP) \
+    hipLaunchKernelGGL((operator_kernel<PP>), dim3(grid_blocks(a)), dim3(kBT), 0, s, a, x, y)
+    switch (a.P) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L
     return hipGetLastError();
 }
 
