@@ -531,11 +531,16 @@ def test_max_iter_reports_not_converged(gpu_lib):
     assert st["outer_iters"] == 2 and np.isfinite(u).all()
 
 
-def test_operator_and_residual_kernels(gpu_lib):
+@pytest.mark.parametrize("nx,ny,P", [(5, 7, 3), (40, 30, 2), (9, 70, 1), (12, 11, 4),
+                                     (100, 12, 3)])
+def test_operator_and_residual_kernels(gpu_lib, nx, ny, P):
+    """Whole-domain S x and the global residual against the oracle's
+    assembled S, on grids spanning several row segments and column blocks
+    of the operator kernel."""
     import torch
     W = gpu_lib
-    h, Xl, Yl = _setup(W, 5, 7, 3, 1, 1, 6.0, _cwave)
-    mesh = sem.Rect(5, 7, 3)
+    h, Xl, Yl = _setup(W, nx, ny, P, 1, 1, 6.0, _cwave)
+    mesh = sem.Rect(nx, ny, P)
     X, Y = sem.node_coords(mesh)
     S, _, _, _ = sem.system(mesh, _cwave(X, Y), 6.0)
     rng = np.random.default_rng(3)
