@@ -197,7 +197,9 @@ int dd_sweep(dd_handle* h, const double* g_re, const double* g_im, const double*
 
 /* Apply the subdomain stiffness A_l (Sec. IV, eq. (4)) to stacked nodal
  * vectors p (n_sub*n_local) with the sweep kernel's own device routine:
- * q = A p.  Host arrays. */
+ * q = A p.  Host arrays.  A_l is the plain stiffness: the extension of the
+ * second-order transmission condition (tc2 > 0) enters the sweeps through
+ * their per-node coefficients, not this routine. */
 int dd_apply_stiffness(dd_handle* h, const double* p, double* q);
 
 /* Relative residual ||b - S u||_2 / ||b||_2 of the global system eq. (4) in
