@@ -120,6 +120,9 @@ typedef struct {
                         and mass keep their Kronecker form, so the time-step rule is
                         unchanged) and adds 2 (q K_side u - omega^2 m u / c^2) / W_side to
                         the interface update; the fixed point stays the global solution.
+                        Useful range about 0.05-0.25: from q omega / c ~ 1 on, the lumped
+                        sweep map has eigenvalues beyond the unit circle (a fixed-point
+                        outer iteration diverges, GMRES slows down).
                         0 = the paper's zeroth-order condition (default). */
 } dd_options;
 

@@ -121,6 +121,25 @@ def test_iteration_operator_contracts_more():
     assert rho[0.0] > 0.99 and rho[0.02] < 0.9, rho
 
 
+def test_large_q_leaves_the_unit_disc():
+    """The condition's limit (documented with its reading): for q omega / c
+    around 1 and above, the lumped discrete sweep map has eigenvalues beyond
+    the unit circle, so a plain fixed-point iteration diverges there (GMRES
+    still converges); q omega / c <= 0.5 keeps them inside."""
+    m = sem.Rect(6, 6, 2)
+    rad = {}
+    for q in (0.08, 0.17):
+        dec = dd.Decomposition(m, dd.Partition(3, 2), np.ones(m.N), 6.0, q=q)
+        idx = np.where(dec.interface_mask())[0]
+        T = np.zeros((idx.size, idx.size), complex)
+        for k, i in enumerate(idx):
+            e = np.zeros(dec.n_if, complex)
+            e[i] = 1.0
+            T[:, k] = dec.sweep(e, np.zeros(m.N), 0.0)[0][idx]
+        rad[q] = np.abs(np.linalg.eigvals(T)).max()
+    assert rad[0.08] < 1.0 + 1e-10 and rad[0.17] > 1.05, rad
+
+
 def test_time_step_rule_still_bounds():
     """The extended weights only add mass where they add stiffness
     (Wx' >= Wx): lambda_max(M'^-1 A') stays below the rule's bound."""
