@@ -20,6 +20,8 @@ Contents (each function cites the passage of the paper it follows):
                  iteration (fixed point and restarted GMRES, Sec. III).
 * ``waveholtz``  The WaveHoltz fixed-point iteration (Sec. V, eqs. (6)-(7),
                  modified leapfrog) and the time-step rule.
+* ``sem3``, ``dd3``  The same discretisation and decomposition on a box with
+                 hexahedral elements (the 3D workload of Sec. VII-B).
 
 Readings taken where the paper is silent or inconsistent are stated in the
 docstrings where they are used (sign of the filter term, the 2/N_t factor,

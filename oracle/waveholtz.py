@@ -126,13 +126,31 @@ def trajectory(A, M, H, b, omega, Nt, u):
     return np.array(out)
 
 
+def time_steps3(P, hx, hy, hz, cmax, omega, safety=0.9):
+    """``time_steps`` for the box: lambda_bar gains the third direction,
+    lambda_bar = cmax^2 mu_hat ((2/hx)^2 + (2/hy)^2 + (2/hz)^2)."""
+    _, w = gll.nodes_weights(P)
+    K = gll.element_stiffness_1d(P)
+    s = 1.0 / np.sqrt(w)
+    mu_hat = np.linalg.eigvalsh(s[:, None] * K * s[None, :]).max()
+    lam = cmax ** 2 * mu_hat * ((2.0 / hx) ** 2 + (2.0 / hy) ** 2 + (2.0 / hz) ** 2)
+    arg = safety * omega / np.sqrt(lam)
+    if arg >= 1.0:
+        return 4
+    return max(4, int(np.ceil(np.pi / np.arcsin(arg))))
+
+
 def subdomain_steps(dec, safety=0.9):
-    """N_t of every subdomain of a Decomposition (c_max over its nodes)."""
+    """N_t of every subdomain of a Decomposition (c_max over its nodes); 2D
+    rectangles or 3D boxes."""
     out = []
     for l in range(dec.L):
         sd = dec.subs[l]
         r = sd["rect"]
-        out.append(time_steps(r.P, r.hx, r.hy, sd["c"].max(), dec.omega, safety))
+        if hasattr(r, "nz"):
+            out.append(time_steps3(r.P, r.hx, r.hy, r.hz, sd["c"].max(), dec.omega, safety))
+        else:
+            out.append(time_steps(r.P, r.hx, r.hy, sd["c"].max(), dec.omega, safety))
     return out
 
 
