@@ -1,0 +1,326 @@
+// 3D box workload (the hexahedral experiments of Sec. VII-B): one DD cycle
+// (Algorithm 1: assemble b, WaveHoltz, interface update) for every box
+// subdomain in one launch, one workgroup per subdomain and one thread per
+// node (the paper's one-DOF-per-thread strategy, up to 1024 nodes per
+// subdomain), and the whole-domain operator y = S x.
+//
+// Stiffness: A = Kx (x) Wy (x) Wz + Wx (x) Ky (x) Wz + Wx (x) Wy (x) Kz applied
+// per node as three (2P+1)-point 1D window sums over a zero-padded copy of
+// p in LDS (double-buffered: one barrier per step); the weights are folded
+// with beta into the per-node coefficients bX, bY, bZ.
+#include "wavedd_internal.h"
+
+namespace wdd {
+
+namespace {
+
+// Deterministic workgroup sum of two FP64 values (butterfly in each wave,
+// then a fixed-order sum over the waves).
+__device__ __forceinline__ void block_sum2_3(double& a, double& b, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = (blockDim.x + 63) >> 6;
+    if (lane == 0) {
+        red[2 * w] = a;
+        red[2 * w + 1] = b;
+    }
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        s0 += red[2 * i];
+        s1 += red[2 * i + 1];
+    }
+    a = s0;
+    b = s1;
+    __syncthreads();
+}
+
+// Assembled 1D reference stiffness row at node k of a line of n_el
+// elements as a (2P+1)-point window centred on k (zero off the line): the
+// node is local a of element e = k / P and, when a = 0 and e > 0, also
+// local P of element e - 1.
+template <typename Real, int P>
+__device__ __forceinline__ void window3(Real (&w)[2 * P + 1], int k, int n_el,
+                                        const double (*K)[kMaxP + 1]) {
+    const int e = k / P, a = k - e * P;
+#pragma unroll
+    for (int t = 0; t <= 2 * P; ++t) {
+        const int d = t - P;
+        double v = 0.0;
+        if (e < n_el && a + d >= 0 && a + d <= P) v += K[a][a + d];
+        if (a == 0 && e > 0 && d <= 0) v += K[P][P + d];
+        w[t] = (Real)v;
+    }
+}
+
+__host__ __device__ inline int box_buf(int nxl, int nyl, int nzl, int P) {
+    return (nxl + 2 * P) * (nyl + 2 * P) * (nzl + 2 * P);
+}
+__host__ __device__ inline int box_tab_off(int nxl, int nyl, int nzl, int P) {
+    return (2 * box_buf(nxl, nyl, nzl, P) + 3) & ~3;
+}
+
+template <typename Real, int P>
+__device__ void sweep3_item(const Sweep3Args<Real>& A, const Sub3& d, int item, Real* lds,
+                            double* red) {
+    constexpr int W = 2 * P + 1;
+    const int nxl = A.nxl, nyl = A.nyl, nzl = A.nzl, tid = threadIdx.x;
+    const int px = nxl + 2 * P, py = nyl + 2 * P;
+    const int nb = box_buf(nxl, nyl, nzl, P);
+    Real* buf0 = lds;
+    Real* buf1 = lds + nb;
+    Real* TAB = lds + box_tab_off(nxl, nyl, nzl, P);
+    for (int i = tid; i < 2 * nb; i += blockDim.x) lds[i] = Real(0);
+    for (int nu = tid; nu < d.nt; nu += blockDim.x) {
+        TAB[4 * nu + 0] = A.cs[d.toff + nu];
+        TAB[4 * nu + 1] = A.sn[d.toff + nu];
+        TAB[4 * nu + 2] = A.kap[d.toff + nu];
+        TAB[4 * nu + 3] = A.kaph[d.toff + nu];
+    }
+    const int nloc = nxl * nyl * nzl;
+    const bool has = tid < nloc;
+    const int t0 = has ? tid : 0;
+    const int il = t0 % nxl, jl = (t0 / nxl) % nyl, kl = t0 / (nxl * nyl);
+    const int pidx = ((kl + P) * py + (jl + P)) * px + (il + P);
+    const int sy = px, sz = px * py;
+    // stiffness windows scaled by the per-node weights beta (2/h) W W: the
+    // off-centre taps of the three directions and one merged centre tap
+    Real cx[W], cy[W], cz[W];
+    window3<Real, P>(cx, il, A.mx, A.K1);
+    window3<Real, P>(cy, jl, A.my, A.K1);
+    window3<Real, P>(cz, kl, A.mz, A.K1);
+    const int64_t n = d.node_off + t0;
+    Real al = Real(0), wc = Real(0), bbr = Real(0), bbi = Real(0);
+    if (has) {
+        al = A.alpha[n];
+        const Real bX = A.betaX[n], bY = A.betaY[n], bZ = A.betaZ[n];
+        wc = bX * cx[P] + bY * cy[P] + bZ * cz[P];
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+            cx[t] *= bX;
+            cy[t] *= bY;
+            cz[t] *= bZ;
+        }
+        // b = src * (f, phi) + sum over the faces through the node of W_face g
+        const double* Wx = A.w1d;
+        const double* Wy = Wx + nxl;
+        const double* Wz = Wy + nyl;
+        double br = 0.0, bi = 0.0;
+        if (A.f_re) {
+            const int64_t gi = d.gbase + ((int64_t)kl * A.Ny + jl) * A.Nx + il;
+            const double v = A.src * (Wx[il] * Wy[jl] * Wz[kl]);
+            br = v * A.f_re[gi];
+            bi = v * A.f_im[gi];
+        }
+        const int64_t o = d.if_off;
+        double2 g;
+        if (il == 0) { g = A.g_in[o + A.face_off[0] + kl * nyl + jl]; br += Wz[kl] * Wy[jl] * g.x; bi += Wz[kl] * Wy[jl] * g.y; }
+        if (il == nxl - 1) { g = A.g_in[o + A.face_off[1] + kl * nyl + jl]; br += Wz[kl] * Wy[jl] * g.x; bi += Wz[kl] * Wy[jl] * g.y; }
+        if (jl == 0) { g = A.g_in[o + A.face_off[2] + kl * nxl + il]; br += Wz[kl] * Wx[il] * g.x; bi += Wz[kl] * Wx[il] * g.y; }
+        if (jl == nyl - 1) { g = A.g_in[o + A.face_off[3] + kl * nxl + il]; br += Wz[kl] * Wx[il] * g.x; bi += Wz[kl] * Wx[il] * g.y; }
+        if (kl == 0) { g = A.g_in[o + A.face_off[4] + jl * nxl + il]; br += Wy[jl] * Wx[il] * g.x; bi += Wy[jl] * Wx[il] * g.y; }
+        if (kl == nzl - 1) { g = A.g_in[o + A.face_off[5] + jl * nxl + il]; br += Wy[jl] * Wx[il] * g.x; bi += Wy[jl] * Wx[il] * g.y; }
+        const double be = (double)A.beta[n];
+        bbr = (Real)(be * br);
+        bbi = (Real)(be * bi);
+    }
+    __syncthreads();
+    const Real sig = (Real)d.sigma;
+    const int nt = d.nt;
+    int it = 0;
+    Real p = Real(0), pd = Real(0), vr = Real(0), vi = Real(0);
+    for (int m = 0; m < A.max_wh; ++m) {
+        // p = Re u, pdot^{1/2} = Re{-i omega u e^{-i pi/N_t}}, v = kappa_0 p + (i/omega) kappa_{1/2} pdot
+        p = pd = Real(0);
+        if (m > 0 && has) {
+            const double2 u = A.u[n];
+            p = (Real)u.x;
+            pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
+        }
+        vr = TAB[2] * p;
+        vi = TAB[3] * pd;
+        for (int nu = 1; nu < nt; ++nu) {
+            Real* buf = (nu & 1) ? buf1 : buf0;
+            const Real c = TAB[4 * nu + 0], sv = TAB[4 * nu + 1];
+            const Real k1 = TAB[4 * nu + 2], k2 = TAB[4 * nu + 3];
+            p = fma(sig, pd, p);
+            if (has) buf[pidx] = p;
+            __syncthreads();
+            // the tap addresses are formed anew each step (an opaque copy
+            // of the index): hoisting all of them out of the loop costs
+            // more registers than the adds it saves
+            int ix = pidx;
+            asm volatile("" : "+v"(ix));
+            const Real* bp = buf + ix;
+            Real acc = wc * p;
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                if (t == P) continue;
+                acc = fma(cx[t], bp[t - P], acc);
+                acc = fma(cy[t], bp[(t - P) * sy], acc);
+                acc = fma(cz[t], bp[(t - P) * sz], acc);
+            }
+            Real tt = bbr * c;
+            tt = fma(bbi, sv, tt);
+            tt -= acc;
+            pd = fma(al, pd, tt);
+            vr = fma(k1, p, vr);
+            vi = fma(k2, pd, vi);
+        }
+        // u = (2/N_t) v (eq. (7)); fixed-point residual of this iteration
+        double dsum = 0.0, nsum = 0.0;
+        if (has) {
+            const double ur = d.two_over_nt * (double)vr, ui = d.two_over_nt * (double)vi;
+            double orr = 0.0, oi = 0.0;
+            if (m > 0) {
+                const double2 o = A.u[n];
+                orr = o.x;
+                oi = o.y;
+            }
+            dsum = (ur - orr) * (ur - orr) + (ui - oi) * (ui - oi);
+            nsum = ur * ur + ui * ui;
+            A.u[n] = make_double2(ur, ui);
+        }
+        block_sum2_3(dsum, nsum, red);
+        it = m + 1;
+        if (!(dsum == dsum)) break;
+        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // interface update (eq. (2)): -g - 2 i (omega/c) u into the neighbour's slot
+    const int f1 = nzl * nyl, f2 = 2 * f1, f3 = f2 + nzl * nxl, f4 = f3 + nzl * nxl,
+              f5 = f4 + nyl * nxl;
+    const int64_t* nbr = A.desc[item].nbr_off;
+    for (int k = tid; k < A.per_sub; k += blockDim.x) {
+        int s, pos, i, j, kk;
+        if (k < f2) {
+            s = k < f1 ? 0 : 1;
+            pos = k - (s ? f1 : 0);
+            kk = pos / nyl;
+            j = pos - kk * nyl;
+            i = s == 0 ? 0 : nxl - 1;
+        } else if (k < f4) {
+            s = k < f3 ? 2 : 3;
+            pos = k - (s == 2 ? f2 : f3);
+            kk = pos / nxl;
+            i = pos - kk * nxl;
+            j = s == 2 ? 0 : nyl - 1;
+        } else {
+            s = k < f5 ? 4 : 5;
+            pos = k - (s == 4 ? f4 : f5);
+            j = pos / nxl;
+            i = pos - j * nxl;
+            kk = s == 4 ? 0 : nzl - 1;
+        }
+        const int64_t dst = nbr[s];
+        if (dst >= 0) {
+            const double2 g = A.g_in[d.if_off + k];
+            const double K = A.kside[d.if_off + k];
+            const double2 u = A.u[d.node_off + ((int64_t)kk * nyl + j) * nxl + i];
+            A.g_out[dst + pos] = make_double2(-g.x + 2.0 * K * u.y, -g.y - 2.0 * K * u.x);
+        } else {
+            A.g_out[d.if_off + k] = make_double2(0.0, 0.0);
+        }
+    }
+    if (tid == 0) A.wh_iters[item] = it;
+}
+
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) sweep3_kernel(const Sweep3Args<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+        const Sub3 d = A.desc[item];
+        sweep3_item<Real, P>(A, d, item, lds, red);
+        __syncthreads();
+    }
+}
+
+// y = S x on the whole box: one thread per node, blocks along grid rows.
+template <int P>
+__global__ void __launch_bounds__(256) operator3_kernel(const Operator3Args A, const double2* x,
+                                                        double2* y) {
+    const int bpr = (A.Nx + 255) / 256;
+    const int row = (int)blockIdx.x / bpr;
+    const int i = ((int)blockIdx.x - row * bpr) * 256 + (int)threadIdx.x;
+    if (i >= A.Nx) return;
+    const int j = row % A.Ny, k = row / A.Ny;
+    const int64_t sj = A.Nx, sk = (int64_t)A.Nx * A.Ny;
+    const int64_t g = (int64_t)k * sk + (int64_t)j * sj + i;
+    double wx[2 * P + 1], wy[2 * P + 1], wz[2 * P + 1];
+    window3<double, P>(wx, i, A.nx, A.K1);
+    window3<double, P>(wy, j, A.ny, A.K1);
+    window3<double, P>(wz, k, A.nz, A.K1);
+    double2 X = make_double2(0.0, 0.0), Y = X, Z = X;
+#pragma unroll
+    for (int t = 0; t <= 2 * P; ++t) {
+        const int di = t - P;
+        if (i + di >= 0 && i + di < A.Nx) {
+            const double2 v = x[g + di];
+            X.x += wx[t] * v.x;
+            X.y += wx[t] * v.y;
+        }
+        if (j + di >= 0 && j + di < A.Ny) {
+            const double2 v = x[g + di * sj];
+            Y.x += wy[t] * v.x;
+            Y.y += wy[t] * v.y;
+        }
+        if (k + di >= 0 && k + di < A.Nz) {
+            const double2 v = x[g + di * sk];
+            Z.x += wz[t] * v.x;
+            Z.y += wz[t] * v.y;
+        }
+    }
+    const double cx = A.sx_ref * A.wy[j] * A.wz[k], cy = A.sy_ref * A.wx[i] * A.wz[k];
+    const double cz = A.sz_ref * A.wx[i] * A.wy[j];
+    const double2 v = x[g];
+    const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
+    y[g] = make_double2(cx * X.x + cy * Y.x + cz * Z.x - m * v.x + h * v.y,
+                        cx * X.y + cy * Y.y + cz * Z.y - m * v.y - h * v.x);
+}
+
+}  // namespace
+
+size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t real_size) {
+    return 40 * sizeof(double) + ((size_t)box_tab_off(nxl, nyl, nzl, P) + 4 * (size_t)nt_max) * real_size;
+}
+
+template <typename Real>
+hipError_t launch_sweep3(const Sweep3Args<Real>& a, int wg, hipStream_t s) {
+    if (wg > kMaxWG) return hipErrorInvalidValue;
+#define L(PP) \
+    hipLaunchKernelGGL((sweep3_kernel<Real, PP>), dim3(a.n_items), dim3(wg), a.lds_bytes, s, a)
+    switch (a.P) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L
+    return hipGetLastError();
+}
+
+hipError_t launch_operator3(const Operator3Args& a, const double2* x, double2* y, hipStream_t s) {
+    const unsigned blocks = (unsigned)(((a.Nx + 255) / 256) * (int64_t)a.Ny * a.Nz);
+#define L(PP) hipLaunchKernelGGL((operator3_kernel<PP>), dim3(blocks), dim3(256), 0, s, a, x, y)
+    switch (a.P) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef L
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep3<double>(const Sweep3Args<double>&, int, hipStream_t);
+template hipError_t launch_sweep3<float>(const Sweep3Args<float>&, int, hipStream_t);
+
+}  // namespace wdd

@@ -1,8 +1,9 @@
 // Host side of the wavedd library: problem setup (GLL tables, lumped
 // coefficients, time-step rule, filter tables), the sweep launcher, the FP64
 // outer GMRES / fixed-point iteration on device vectors, and the C ABI of
-// include/wavedd.h.
+// include/wavedd.h, and the box (3D) sweep of include/wavedd3.h.
 #include "../../include/wavedd.h"
+#include "../../include/wavedd3.h"
 
 #include <hip/hip_runtime.h>
 
@@ -2585,6 +2586,562 @@ int dd_engine_get_info(dd_engine* e, dd_engine_info* info) {
     info->store_bytes = e->store->bytes;
     info->request_bytes = e->used;
     info->launches = e->store->sched.launches.load();
+    return DD_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Box (3D) decomposition: setup, sweep and operator of include/wavedd3.h
+// ===========================================================================
+struct dd3_handle {
+    dd_box box{};
+    dd_partition3 part{};
+    dd_options opt{};
+    int P = 0, dev = 0;
+    double omega = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
+    int mx = 0, my = 0, mz = 0, nxl = 0, nyl = 0, nzl = 0, Nx = 0, Ny = 0, Nz = 0;
+    int64_t N = 0, nloc = 0, L = 0, per_sub = 0, n_if = 0, tab_len = 0;
+    int face_off[6] = {0, 0, 0, 0, 0, 0};
+    int nt_max = 0;
+    std::vector<int> nt;
+    std::vector<wdd::Sub3> desc;
+    double K1[wdd::kMaxP + 1][wdd::kMaxP + 1] = {};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DBuf<wdd::Sub3> d_desc;
+    DBuf<unsigned char> d_coef;  // alpha, betaX, betaY, betaZ, beta (Real, nn each)
+    DBuf<unsigned char> d_tab;   // kap, kaph, cs, sn (Real, tab_len each)
+    DBuf<double> d_w1d, d_kside, d_wx, d_wy, d_wz, d_M, d_H, d_f;
+    DBuf<double2> d_gin, d_gout, d_u;
+    DBuf<int> d_iters;
+    bool has_f = false;
+};
+
+namespace {
+
+void dd3_free(dd3_handle* h) {
+    h->d_desc.free();
+    h->d_coef.free();
+    h->d_tab.free();
+    for (DBuf<double>* b : {&h->d_w1d, &h->d_kside, &h->d_wx, &h->d_wy, &h->d_wz, &h->d_M, &h->d_H,
+                            &h->d_f})
+        b->free();
+    h->d_gin.free();
+    h->d_gout.free();
+    h->d_u.free();
+    h->d_iters.free();
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    h->ev0 = h->ev1 = nullptr;
+    h->stream = nullptr;
+}
+
+int validate3(const dd3_handle* h) {
+    if (!h || h->L < 1) return fail(DD_EINVAL, "null or unset 3D handle");
+    return DD_OK;
+}
+
+size_t real3(const dd3_handle* h) { return h->opt.precision == DD_FP32 ? 4 : 8; }
+
+// Physical lumped 1D weights of a line of m elements of length h.
+std::vector<double> line_weights(const Gll& g, int m, double hlen) {
+    std::vector<double> w(m * g.P + 1);
+    for (int i = 0; i <= m * g.P; ++i) w[i] = 0.5 * hlen * wref(g, i, m);
+    return w;
+}
+
+// Time steps per period on a box element (Sec. V bound with the z term).
+int time_steps3(const Gll& g, double hx, double hy, double hz, double cmax, double omega,
+                double cfl) {
+    const double lam = cmax * cmax * g.mu *
+                       ((2.0 / hx) * (2.0 / hx) + (2.0 / hy) * (2.0 / hy) + (2.0 / hz) * (2.0 / hz));
+    const double arg = cfl * omega / std::sqrt(lam);
+    if (arg >= 1.0) return 4;
+    return std::max(4, (int)std::ceil(M_PI / std::asin(arg)));
+}
+
+template <typename Real>
+int upload_real(unsigned char* dst, const std::vector<double>& v) {
+    std::vector<Real> r(v.size());
+    for (size_t i = 0; i < v.size(); ++i) r[i] = (Real)v[i];
+    HIPCHK(hipMemcpy(dst, r.data(), sizeof(Real) * r.size(), hipMemcpyHostToDevice));
+    return DD_OK;
+}
+
+int upload_as(const dd3_handle* h, unsigned char* dst, const std::vector<double>& v) {
+    return h->opt.precision == DD_FP32 ? upload_real<float>(dst, v) : upload_real<double>(dst, v);
+}
+
+int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, double omega,
+             const dd_partition3* part, const dd_options* opt) {
+    if (!box || !part || !c) return fail(DD_EINVAL, "null box, partition or wavespeed");
+    if (degree < 1 || degree > wdd::kMaxP)
+        return fail(DD_EINVAL, "degree %d not in [1, %d]", degree, wdd::kMaxP);
+    if (box->nx < 1 || box->ny < 1 || box->nz < 1) return fail(DD_EINVAL, "empty box");
+    const double lo[3] = {box->x0, box->y0, box->z0}, hi[3] = {box->x1, box->y1, box->z1};
+    for (int d = 0; d < 3; ++d)
+        if (!(hi[d] > lo[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d]))
+            return fail(DD_EINVAL, "degenerate box");
+    if (!(omega > 0.0) || !std::isfinite(omega)) return fail(DD_EINVAL, "omega must be > 0");
+    if (part->sx < 1 || part->sy < 1 || part->sz < 1 || box->nx % part->sx ||
+        box->ny % part->sy || box->nz % part->sz)
+        return fail(DD_EINVAL, "partition %dx%dx%d does not divide box %dx%dx%d", part->sx,
+                    part->sy, part->sz, box->nx, box->ny, box->nz);
+    dd_options o;
+    if (opt)
+        o = *opt;
+    else
+        dd_default_options(&o);
+    if (o.precision != DD_FP64 && o.precision != DD_FP32) return fail(DD_EINVAL, "bad precision");
+    if (o.max_wh < 1) return fail(DD_EINVAL, "max_wh must be >= 1");
+    if (!(o.cfl > 0.0 && o.cfl <= 1.0)) return fail(DD_EINVAL, "cfl must be in (0, 1]");
+    if (o.nt_override < 0 || o.nt_override == 1 || o.nt_override == 2)
+        return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
+    if (!std::isfinite(o.tau_in)) return fail(DD_EINVAL, "tau_in must be finite");
+    const int P = degree;
+    const int64_t Nx = (int64_t)box->nx * P + 1, Ny = (int64_t)box->ny * P + 1,
+                  Nz = (int64_t)box->nz * P + 1;
+    if (Nx * Ny * Nz > (int64_t)2000000000) return fail(DD_EINVAL, "box too large");
+    const int mx = box->nx / part->sx, my = box->ny / part->sy, mz = box->nz / part->sz;
+    const int nxl = mx * P + 1, nyl = my * P + 1, nzl = mz * P + 1;
+    if ((int64_t)nxl * nyl * nzl > wdd::kMaxWG)
+        return fail(DD_EINVAL, "subdomain of %dx%dx%d nodes exceeds 1024 (one node per thread)",
+                    nxl, nyl, nzl);
+    h->box = *box;
+    h->part = *part;
+    h->opt = o;
+    h->P = P;
+    h->omega = omega;
+    h->Nx = (int)Nx;
+    h->Ny = (int)Ny;
+    h->Nz = (int)Nz;
+    h->N = Nx * Ny * Nz;
+    for (int64_t i = 0; i < h->N; ++i)
+        if (!(c[i] > 0.0) || !std::isfinite(c[i]))
+            return fail(DD_EINVAL, "wavespeed[%lld] = %g is not a positive number", (long long)i,
+                        c[i]);
+    h->mx = mx;
+    h->my = my;
+    h->mz = mz;
+    h->nxl = nxl;
+    h->nyl = nyl;
+    h->nzl = nzl;
+    h->nloc = (int64_t)nxl * nyl * nzl;
+    h->L = (int64_t)part->sx * part->sy * part->sz;
+    const int flen[6] = {nyl * nzl, nyl * nzl, nxl * nzl, nxl * nzl, nxl * nyl, nxl * nyl};
+    int acc = 0;
+    for (int s = 0; s < 6; ++s) {
+        h->face_off[s] = acc;
+        acc += flen[s];
+    }
+    h->per_sub = acc;
+    h->n_if = h->L * h->per_sub;
+    h->hx = (box->x1 - box->x0) / box->nx;
+    h->hy = (box->y1 - box->y0) / box->ny;
+    h->hz = (box->z1 - box->z0) / box->nz;
+    const Gll g = make_gll(P);
+    for (int a = 0; a <= P; ++a)
+        for (int b = 0; b <= P; ++b) h->K1[a][b] = g.K[a][b];
+
+    const int64_t L = h->L, nloc = h->nloc, nn = L * nloc;
+    auto gnode = [&](int64_t l, int il, int jl, int kl) {
+        const int a = (int)(l % part->sx), b = (int)((l / part->sx) % part->sy),
+                  cc = (int)(l / ((int64_t)part->sx * part->sy));
+        return ((int64_t)(cc * mz * P + kl) * Ny + (b * my * P + jl)) * Nx + a * mx * P + il;
+    };
+    // time steps and filter tables (deduplicated by N_t), as in the 2D setup
+    h->nt.resize(L);
+    std::map<int, int> toff;
+    std::vector<double> kap, kaph, cs, sn;
+    for (int64_t l = 0; l < L; ++l) {
+        double cmax = 0.0;
+        for (int kl = 0; kl < nzl; ++kl)
+            for (int jl = 0; jl < nyl; ++jl)
+                for (int il = 0; il < nxl; ++il) cmax = std::max(cmax, c[gnode(l, il, jl, kl)]);
+        const int n = o.nt_override > 0 ? o.nt_override
+                                        : time_steps3(g, h->hx, h->hy, h->hz, cmax, omega, o.cfl);
+        h->nt[l] = n;
+        if (!toff.count(n)) {
+            toff[n] = (int)kap.size();
+            const double k0 = -0.25 + 0.25 * std::tan(M_PI / n) * std::tan(M_PI / n);
+            for (int nu = 0; nu < n; ++nu) {
+                kap.push_back(std::cos(2.0 * M_PI * nu / n) + k0);
+                kaph.push_back((std::cos(2.0 * M_PI * (nu + 0.5) / n) + k0) / omega);
+                cs.push_back(std::cos(2.0 * M_PI * nu / n));
+                sn.push_back(std::sin(2.0 * M_PI * nu / n));
+            }
+        }
+    }
+    h->tab_len = (int64_t)kap.size();
+    h->nt_max = *std::max_element(h->nt.begin(), h->nt.end());
+    if (wdd::sweep3_lds_bytes(nxl, nyl, nzl, P, h->nt_max, real3(h)) > kLdsLimit)
+        return fail(DD_EINVAL, "subdomain %dx%dx%d nodes (P=%d, N_t=%d) exceeds the LDS", nxl,
+                    nyl, nzl, P, h->nt_max);
+
+    // per-node coefficients (Sec. IV lumped M, H; Sec. V alpha, beta)
+    const std::vector<double> wx = line_weights(g, mx, h->hx), wy = line_weights(g, my, h->hy),
+                              wz = line_weights(g, mz, h->hz);
+    std::vector<double> alpha(nn), bX(nn), bY(nn), bZ(nn), beta(nn), kside(h->n_if);
+    h->desc.resize(L);
+    for (int64_t l = 0; l < L; ++l) {
+        const int n = h->nt[l];
+        const double half = M_PI / n;
+        const double theta = std::tan(half) / omega;
+        const double sigma = std::sin(half) / (0.5 * omega);
+        for (int kl = 0; kl < nzl; ++kl)
+            for (int jl = 0; jl < nyl; ++jl)
+                for (int il = 0; il < nxl; ++il) {
+                    const int64_t k = l * nloc + ((int64_t)kl * nyl + jl) * nxl + il;
+                    const double cc = c[gnode(l, il, jl, kl)];
+                    const double M = wx[il] * wy[jl] * wz[kl] / (cc * cc);
+                    double Hs = 0.0;
+                    if (il == 0) Hs += wy[jl] * wz[kl];
+                    if (il == nxl - 1) Hs += wy[jl] * wz[kl];
+                    if (jl == 0) Hs += wx[il] * wz[kl];
+                    if (jl == nyl - 1) Hs += wx[il] * wz[kl];
+                    if (kl == 0) Hs += wx[il] * wy[jl];
+                    if (kl == nzl - 1) Hs += wx[il] * wy[jl];
+                    const double H = Hs / cc;
+                    alpha[k] = (M - theta * H) / (M + theta * H);
+                    beta[k] = sigma / (M + theta * H);
+                    bX[k] = beta[k] * (2.0 / h->hx) * wy[jl] * wz[kl];
+                    bY[k] = beta[k] * (2.0 / h->hy) * wx[il] * wz[kl];
+                    bZ[k] = beta[k] * (2.0 / h->hz) * wx[il] * wy[jl];
+                }
+        // omega / c at every face slot, in the g layout
+        const int64_t o = l * h->per_sub;
+        for (int kl = 0; kl < nzl; ++kl)
+            for (int jl = 0; jl < nyl; ++jl) {
+                kside[o + h->face_off[0] + kl * nyl + jl] = omega / c[gnode(l, 0, jl, kl)];
+                kside[o + h->face_off[1] + kl * nyl + jl] = omega / c[gnode(l, nxl - 1, jl, kl)];
+            }
+        for (int kl = 0; kl < nzl; ++kl)
+            for (int il = 0; il < nxl; ++il) {
+                kside[o + h->face_off[2] + kl * nxl + il] = omega / c[gnode(l, il, 0, kl)];
+                kside[o + h->face_off[3] + kl * nxl + il] = omega / c[gnode(l, il, nyl - 1, kl)];
+            }
+        for (int jl = 0; jl < nyl; ++jl)
+            for (int il = 0; il < nxl; ++il) {
+                kside[o + h->face_off[4] + jl * nxl + il] = omega / c[gnode(l, il, jl, 0)];
+                kside[o + h->face_off[5] + jl * nxl + il] = omega / c[gnode(l, il, jl, nzl - 1)];
+            }
+        wdd::Sub3& d = h->desc[l];
+        d = wdd::Sub3{};
+        d.nt = n;
+        d.toff = toff[n];
+        d.node_off = l * nloc;
+        d.if_off = o;
+        d.gbase = gnode(l, 0, 0, 0);
+        const int a = (int)(l % part->sx), b = (int)((l / part->sx) % part->sy),
+                  cc = (int)(l / ((int64_t)part->sx * part->sy));
+        const int da[6] = {-1, 1, 0, 0, 0, 0}, db[6] = {0, 0, -1, 1, 0, 0},
+                  dc[6] = {0, 0, 0, 0, -1, 1}, opp[6] = {1, 0, 3, 2, 5, 4};
+        for (int s = 0; s < 6; ++s) {
+            const int a2 = a + da[s], b2 = b + db[s], c2 = cc + dc[s];
+            if (a2 < 0 || a2 >= part->sx || b2 < 0 || b2 >= part->sy || c2 < 0 || c2 >= part->sz) {
+                d.nbr_off[s] = -1;
+            } else {
+                const int64_t r = ((int64_t)c2 * part->sy + b2) * part->sx + a2;
+                d.nbr_off[s] = r * h->per_sub + h->face_off[opp[s]];
+            }
+        }
+        d.sigma = sigma;
+        d.pd0c = omega * std::cos(M_PI / n);
+        d.pd0s = omega * std::sin(M_PI / n);
+        d.two_over_nt = 2.0 / n;
+    }
+
+    // global 1D weights, lumped M and H for the whole-box operator
+    const std::vector<double> gx = line_weights(g, box->nx, h->hx),
+                              gy = line_weights(g, box->ny, h->hy),
+                              gz = line_weights(g, box->nz, h->hz);
+    std::vector<double> Mg(h->N), Hg(h->N);
+    for (int64_t k = 0; k < Nz; ++k)
+        for (int64_t j = 0; j < Ny; ++j)
+            for (int64_t i = 0; i < Nx; ++i) {
+                const int64_t q = (k * Ny + j) * Nx + i;
+                Mg[q] = gx[i] * gy[j] * gz[k] / (c[q] * c[q]);
+                double Hs = 0.0;
+                if (i == 0 || i == Nx - 1) Hs += gy[j] * gz[k] * ((i == 0) + (i == Nx - 1));
+                if (j == 0 || j == Ny - 1) Hs += gx[i] * gz[k] * ((j == 0) + (j == Ny - 1));
+                if (k == 0 || k == Nz - 1) Hs += gx[i] * gy[j] * ((k == 0) + (k == Nz - 1));
+                Hg[q] = Hs / c[q];
+            }
+
+    // device buffers
+    CHK(device_present(&h->dev));
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&h->ev0));
+    HIPCHK(hipEventCreate(&h->ev1));
+    const size_t rs = real3(h);
+    HIPCHK(h->d_desc.alloc(L));
+    HIPCHK(h->d_coef.alloc(5 * nn * rs));
+    HIPCHK(h->d_tab.alloc(4 * h->tab_len * rs));
+    HIPCHK(h->d_w1d.alloc(nxl + nyl + nzl));
+    HIPCHK(h->d_kside.alloc(h->n_if));
+    HIPCHK(h->d_wx.alloc(Nx));
+    HIPCHK(h->d_wy.alloc(Ny));
+    HIPCHK(h->d_wz.alloc(Nz));
+    HIPCHK(h->d_M.alloc(h->N));
+    HIPCHK(h->d_H.alloc(h->N));
+    HIPCHK(h->d_f.alloc(2 * h->N));
+    HIPCHK(h->d_gin.alloc(h->n_if));
+    HIPCHK(h->d_gout.alloc(h->n_if));
+    HIPCHK(h->d_u.alloc(nn));
+    HIPCHK(h->d_iters.alloc(L));
+    HIPCHK(hipMemcpy(h->d_desc.p, h->desc.data(), sizeof(wdd::Sub3) * L, hipMemcpyHostToDevice));
+    const std::vector<double>* coefs[5] = {&alpha, &bX, &bY, &bZ, &beta};
+    for (int i = 0; i < 5; ++i) CHK(upload_as(h, h->d_coef.p + i * nn * rs, *coefs[i]));
+    const std::vector<double>* tabs[4] = {&kap, &kaph, &cs, &sn};
+    for (int i = 0; i < 4; ++i) CHK(upload_as(h, h->d_tab.p + i * h->tab_len * rs, *tabs[i]));
+    std::vector<double> w1d;
+    w1d.insert(w1d.end(), wx.begin(), wx.end());
+    w1d.insert(w1d.end(), wy.begin(), wy.end());
+    w1d.insert(w1d.end(), wz.begin(), wz.end());
+    HIPCHK(hipMemcpy(h->d_w1d.p, w1d.data(), 8 * w1d.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_kside.p, kside.data(), 8 * kside.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_wx.p, gx.data(), 8 * gx.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_wy.p, gy.data(), 8 * gy.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_wz.p, gz.data(), 8 * gz.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_M.p, Mg.data(), 8 * Mg.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d_H.p, Hg.data(), 8 * Hg.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(h->d_gin.p, 0, sizeof(double2) * h->n_if));
+    HIPCHK(hipMemset(h->d_u.p, 0, sizeof(double2) * nn));
+    return DD_OK;
+}
+
+template <typename Real>
+wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, double src, bool with_f, double tau,
+                                  int max_wh) {
+    wdd::Sweep3Args<Real> a{};
+    const int64_t nn = h->L * h->nloc;
+    const Real* coef = reinterpret_cast<const Real*>(h->d_coef.p);
+    const Real* tab = reinterpret_cast<const Real*>(h->d_tab.p);
+    a.desc = h->d_desc.p;
+    a.n_items = (int)h->L;
+    a.nxl = h->nxl;
+    a.nyl = h->nyl;
+    a.nzl = h->nzl;
+    a.mx = h->mx;
+    a.my = h->my;
+    a.mz = h->mz;
+    a.P = h->P;
+    a.per_sub = (int)h->per_sub;
+    for (int s = 0; s < 6; ++s) a.face_off[s] = h->face_off[s];
+    a.alpha = coef;
+    a.betaX = coef + nn;
+    a.betaY = coef + 2 * nn;
+    a.betaZ = coef + 3 * nn;
+    a.beta = coef + 4 * nn;
+    a.Nx = h->Nx;
+    a.Ny = h->Ny;
+    a.f_re = with_f ? h->d_f.p : nullptr;
+    a.f_im = with_f ? h->d_f.p + h->N : nullptr;
+    a.w1d = h->d_w1d.p;
+    a.kside = h->d_kside.p;
+    a.kap = tab;
+    a.kaph = tab + h->tab_len;
+    a.cs = tab + 2 * h->tab_len;
+    a.sn = tab + 3 * h->tab_len;
+    a.g_in = h->d_gin.p;
+    a.g_out = h->d_gout.p;
+    a.src = src;
+    a.u = h->d_u.p;
+    a.wh_iters = h->d_iters.p;
+    a.tau = tau;
+    a.max_wh = max_wh;
+    a.lds_bytes = wdd::sweep3_lds_bytes(h->nxl, h->nyl, h->nzl, h->P, h->nt_max, sizeof(Real));
+    for (int i = 0; i <= h->P; ++i)
+        for (int j = 0; j <= h->P; ++j) a.K1[i][j] = h->K1[i][j];
+    return a;
+}
+
+// One launch over all box subdomains; optionally timed with events.
+int run_sweep3(dd3_handle* h, double src, bool with_f, double tau, int max_wh, float* ms) {
+    const int wg = (int)(((h->nloc + 63) / 64) * 64);
+    if (ms) HIPCHK(hipEventRecord(h->ev0, h->stream));
+    hipError_t e;
+    if (h->opt.precision == DD_FP32)
+        e = wdd::launch_sweep3<float>(sweep3_args<float>(h, src, with_f, tau, max_wh), wg, h->stream);
+    else
+        e = wdd::launch_sweep3<double>(sweep3_args<double>(h, src, with_f, tau, max_wh), wg,
+                                       h->stream);
+    HIPCHK(e);
+    if (ms) HIPCHK(hipEventRecord(h->ev1, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (ms) HIPCHK(hipEventElapsedTime(ms, h->ev0, h->ev1));
+    return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dd3_destroy(dd3_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipSetDevice(h->dev);
+    dd3_free(h);
+    delete h;
+}
+
+int dd3_setup(dd3_handle** out, const dd_box* box, int degree, const double* wavespeed,
+              double omega, const dd_partition3* part, const dd_options* opt) {
+    if (!out) return fail(DD_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    dd3_handle* h = new dd3_handle();
+    const int rc = prepare3(h, box, degree, wavespeed, omega, part, opt);
+    if (rc != DD_OK) {
+        dd3_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return DD_OK;
+}
+
+int dd3_sizes(const dd3_handle* h, int64_t* n_global, int64_t* n_local, int64_t* n_sub,
+              int64_t* n_iface) {
+    CHK(validate3(h));
+    if (n_global) *n_global = h->N;
+    if (n_local) *n_local = h->nloc;
+    if (n_sub) *n_sub = h->L;
+    if (n_iface) *n_iface = h->n_if;
+    return DD_OK;
+}
+
+int dd3_time_steps(const dd3_handle* h, int* nt) {
+    CHK(validate3(h));
+    if (!nt) return fail(DD_EINVAL, "null output");
+    std::copy(h->nt.begin(), h->nt.end(), nt);
+    return DD_OK;
+}
+
+int dd3_mesh_coords(const dd_box* box, int degree, double* x, double* y, double* z) {
+    if (!box || !x || !y || !z) return fail(DD_EINVAL, "null argument");
+    if (degree < 1 || degree > wdd::kMaxP)
+        return fail(DD_EINVAL, "degree %d not in [1, %d]", degree, wdd::kMaxP);
+    if (box->nx < 1 || box->ny < 1 || box->nz < 1) return fail(DD_EINVAL, "empty box");
+    const Gll g = make_gll(degree);
+    const int P = degree;
+    auto axis = [&](int n, double a, double b) {
+        const double hh = (b - a) / n;
+        std::vector<double> v(n * P + 1);
+        for (int e = 0; e < n; ++e)
+            for (int q = 0; q <= P; ++q) v[e * P + q] = a + e * hh + 0.5 * hh * (g.x[q] + 1.0);
+        v[n * P] = b;
+        return v;
+    };
+    const std::vector<double> xs = axis(box->nx, box->x0, box->x1),
+                              ys = axis(box->ny, box->y0, box->y1),
+                              zs = axis(box->nz, box->z0, box->z1);
+    int64_t q = 0;
+    for (double zz : zs)
+        for (double yy : ys)
+            for (double xx : xs) {
+                x[q] = xx;
+                y[q] = yy;
+                z[q] = zz;
+                ++q;
+            }
+    return DD_OK;
+}
+
+int dd3_sweep(dd3_handle* h, const double* g_re, const double* g_im, const double* f_re,
+              const double* f_im, double src, double* g_out_re, double* g_out_im, double* u_re,
+              double* u_im, int* wh_iters) {
+    CHK(validate3(h));
+    if (!g_out_re || !g_out_im) return fail(DD_EINVAL, "null output");
+    if (!std::isfinite(src)) return fail(DD_EINVAL, "src must be finite");
+    if (!f_re && f_im) return fail(DD_EINVAL, "f_im given without f_re");
+    CHK(check_finite(g_re, h->n_if, "g_re"));
+    CHK(check_finite(g_im, h->n_if, "g_im"));
+    CHK(check_finite(f_re, h->N, "f_re"));
+    CHK(check_finite(f_im, h->N, "f_im"));
+    HIPCHK(hipSetDevice(h->dev));
+    std::vector<double2> gi(h->n_if);
+    for (int64_t i = 0; i < h->n_if; ++i)
+        gi[i] = make_double2(g_re ? g_re[i] : 0.0, g_im ? g_im[i] : 0.0);
+    HIPCHK(hipMemcpy(h->d_gin.p, gi.data(), sizeof(double2) * h->n_if, hipMemcpyHostToDevice));
+    const bool with_f = f_re != nullptr;
+    if (with_f) {
+        HIPCHK(hipMemcpy(h->d_f.p, f_re, 8 * h->N, hipMemcpyHostToDevice));
+        if (f_im)
+            HIPCHK(hipMemcpy(h->d_f.p + h->N, f_im, 8 * h->N, hipMemcpyHostToDevice));
+        else
+            HIPCHK(hipMemset(h->d_f.p + h->N, 0, 8 * h->N));
+    }
+    const double tau = h->opt.tau_in > 0.0 ? h->opt.tau_in : 0.0;
+    CHK(run_sweep3(h, src, with_f, tau, h->opt.max_wh, nullptr));
+    HIPCHK(hipMemcpy(gi.data(), h->d_gout.p, sizeof(double2) * h->n_if, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < h->n_if; ++i) {
+        g_out_re[i] = gi[i].x;
+        g_out_im[i] = gi[i].y;
+    }
+    if (u_re || u_im) {
+        std::vector<double2> u(h->L * h->nloc);
+        HIPCHK(hipMemcpy(u.data(), h->d_u.p, sizeof(double2) * u.size(), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < u.size(); ++i) {
+            if (u_re) u_re[i] = u[i].x;
+            if (u_im) u_im[i] = u[i].y;
+        }
+    }
+    if (wh_iters)
+        HIPCHK(hipMemcpy(wh_iters, h->d_iters.p, sizeof(int) * h->L, hipMemcpyDeviceToHost));
+    return DD_OK;
+}
+
+int dd3_time_sweep(dd3_handle* h, int reps, int fixed_iters, double* ms, double* dof_updates) {
+    CHK(validate3(h));
+    if (reps < 1 || !ms || fixed_iters < 0)
+        return fail(DD_EINVAL, "reps must be >= 1, fixed_iters >= 0, ms non-null");
+    HIPCHK(hipSetDevice(h->dev));
+    const double tau = fixed_iters > 0 ? 0.0 : std::max(h->opt.tau_in, 0.0);
+    const int mwh = fixed_iters > 0 ? fixed_iters : h->opt.max_wh;
+    float t = 0.f;
+    CHK(run_sweep3(h, 0.0, false, tau, mwh, &t));
+    double total = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        CHK(run_sweep3(h, 0.0, false, tau, mwh, &t));
+        total += t;
+    }
+    *ms = total / reps;
+    if (dof_updates) {
+        std::vector<int> its(h->L);
+        HIPCHK(hipMemcpy(its.data(), h->d_iters.p, sizeof(int) * h->L, hipMemcpyDeviceToHost));
+        double du = 0.0;
+        for (int64_t l = 0; l < h->L; ++l) du += (double)h->nloc * (h->nt[l] - 1) * its[l];
+        *dof_updates = du;
+    }
+    return DD_OK;
+}
+
+int dd3_apply_operator_device(dd3_handle* h, void* stream, const double* d_x, double* d_y) {
+    CHK(validate3(h));
+    if (!d_x || !d_y) return fail(DD_EINVAL, "null array");
+    HIPCHK(hipSetDevice(h->dev));
+    wdd::Operator3Args a{};
+    a.Nx = h->Nx;
+    a.Ny = h->Ny;
+    a.Nz = h->Nz;
+    a.P = h->P;
+    a.nx = h->box.nx;
+    a.ny = h->box.ny;
+    a.nz = h->box.nz;
+    a.sx_ref = 2.0 / h->hx;
+    a.sy_ref = 2.0 / h->hy;
+    a.sz_ref = 2.0 / h->hz;
+    a.wx = h->d_wx.p;
+    a.wy = h->d_wy.p;
+    a.wz = h->d_wz.p;
+    a.M = h->d_M.p;
+    a.H = h->d_H.p;
+    a.omega = h->omega;
+    for (int i = 0; i <= h->P; ++i)
+        for (int j = 0; j <= h->P; ++j) a.K1[i][j] = h->K1[i][j];
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    HIPCHK(wdd::launch_operator3(a, (const double2*)d_x, (double2*)d_y, s));
     return DD_OK;
 }
 

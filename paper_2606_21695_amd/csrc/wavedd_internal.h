@@ -154,4 +154,67 @@ hipError_t launch_residual(const OperatorArgs& a, const double2* u, const double
 // b.result[0] = sum of v (both components), deterministic.
 hipError_t blas_sum2(Blas& b, const double2* v, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// 3D box decomposition: one work item per box subdomain, one thread per node.
+struct Sub3 {
+    int nt;              // leapfrog steps per period
+    int toff;            // offset of this subdomain's filter tables
+    int64_t node_off;    // first local node in the per-node arrays
+    int64_t if_off;      // first slot of its six faces (x0, x1, y0, y1, z0, z1)
+    int64_t nbr_off[6];  // first slot of the neighbour face receiving each face, -1: outer
+    int64_t gbase;       // global index of its local node (0, 0, 0)
+    double sigma;        // leapfrog step sin(omega dt / 2) / (omega / 2)
+    double pd0c, pd0s;   // omega cos(pi/N_t), omega sin(pi/N_t)
+    double two_over_nt;  // 2 / N_t
+};
+
+template <typename Real>
+struct Sweep3Args {
+    const Sub3* desc;
+    int n_items;
+    int nxl, nyl, nzl, mx, my, mz, P;
+    int per_sub;             // interface slots per subdomain
+    int face_off[6];         // first slot of each face within a subdomain
+    const Real* alpha;       // (M - theta H) / (M + theta H)
+    const Real* betaX;       // beta * (2/hx) * Wy * Wz
+    const Real* betaY;       // beta * (2/hy) * Wx * Wz
+    const Real* betaZ;       // beta * (2/hz) * Wx * Wy
+    const Real* beta;        // sigma / (M + theta H)
+    int Nx, Ny;              // global node grid (x and y extents) for indexing f
+    const double* f_re;      // source f at the global nodes, or null
+    const double* f_im;
+    const double* w1d;       // physical lumped 1D weights of a subdomain: x, then y, then z
+    const double* kside;     // omega / c per interface slot
+    const Real* kap;         // kappa(nu)
+    const Real* kaph;        // kappa(nu + 1/2) / omega
+    const Real* cs;          // cos(2 pi nu / N_t)
+    const Real* sn;          // sin(2 pi nu / N_t)
+    const double2* g_in;
+    double2* g_out;
+    double src;
+    double2* u;
+    int* wh_iters;
+    double tau;
+    int max_wh;
+    size_t lds_bytes;
+    double K1[kMaxP + 1][kMaxP + 1];  // reference D^T W D of degree P
+};
+template <typename Real>
+hipError_t launch_sweep3(const Sweep3Args<Real>& a, int wg, hipStream_t s);
+size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t real_size);
+
+// Whole-box operator y = S x (FP64) on the global node grid.
+struct Operator3Args {
+    int Nx, Ny, Nz, P, nx, ny, nz;
+    double sx_ref, sy_ref, sz_ref;  // 2/hx, 2/hy, 2/hz
+    const double* wx;               // assembled physical 1D weights (Nx, Ny, Nz)
+    const double* wy;
+    const double* wz;
+    const double* M;
+    const double* H;
+    double omega;
+    double K1[kMaxP + 1][kMaxP + 1];
+};
+hipError_t launch_operator3(const Operator3Args& a, const double2* x, double2* y, hipStream_t s);
+
 }  // namespace wdd

@@ -31,6 +31,8 @@ EXPORTS = [
     "dd_batch_solve_start", "dd_batch_solve_finish",
     "dd_engine_create", "dd_engine_destroy", "dd_engine_submit", "dd_engine_status",
     "dd_engine_wait", "dd_engine_get_info", "dd_engine_wait_any", "dd_set_progress",
+    "dd3_setup", "dd3_destroy", "dd3_sizes", "dd3_time_steps", "dd3_mesh_coords", "dd3_sweep",
+    "dd3_time_sweep", "dd3_apply_operator_device",
 ]
 DD_REQ_QUEUED, DD_REQ_RUNNING, DD_REQ_DONE = 0, 1, 2
 
@@ -42,6 +44,16 @@ class dd_mesh(C.Structure):
 
 class dd_partition(C.Structure):
     _fields_ = [("sx", C.c_int), ("sy", C.c_int)]
+
+
+class dd_box(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("z0", C.c_double), ("z1", C.c_double), ("nx", C.c_int), ("ny", C.c_int),
+                ("nz", C.c_int)]
+
+
+class dd_partition3(C.Structure):
+    _fields_ = [("sx", C.c_int), ("sy", C.c_int), ("sz", C.c_int)]
 
 
 class dd_options(C.Structure):
@@ -166,6 +178,15 @@ def load():
         "dd_engine_get_info": ([P, C.POINTER(dd_engine_info)], C.c_int),
         "dd_engine_wait_any": ([P, I64], C.c_int),
         "dd_set_progress": ([P, PROGRESS_FN, P, C.c_int], C.c_int),
+        "dd3_setup": ([C.POINTER(P), C.POINTER(dd_box), C.c_int, D, C.c_double,
+                       C.POINTER(dd_partition3), C.POINTER(dd_options)], C.c_int),
+        "dd3_destroy": ([P], None),
+        "dd3_sizes": ([P, I64, I64, I64, I64], C.c_int),
+        "dd3_time_steps": ([P, C.POINTER(C.c_int)], C.c_int),
+        "dd3_mesh_coords": ([C.POINTER(dd_box), C.c_int, D, D, D], C.c_int),
+        "dd3_sweep": ([P, D, D, D, D, C.c_double, D, D, D, D, C.POINTER(C.c_int)], C.c_int),
+        "dd3_time_sweep": ([P, C.c_int, C.c_int, D, D], C.c_int),
+        "dd3_apply_operator_device": ([P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -551,3 +572,81 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Box (3D) decomposition, include/wavedd3.h
+# ---------------------------------------------------------------------------
+def dd3_setup(nx, ny, nz, degree, wavespeed, omega, sx, sy, sz, x0=-1.0, x1=1.0, y0=-1.0,
+              y1=1.0, z0=-1.0, z1=1.0, options=None):
+    """Create a box handle (returns an opaque c_void_p)."""
+    lib = load()
+    box = dd_box(x0, x1, y0, y1, z0, z1, nx, ny, nz)
+    part = dd_partition3(sx, sy, sz)
+    c = _f64(wavespeed)
+    h = C.c_void_p()
+    _check(lib.dd3_setup(C.byref(h), C.byref(box), degree, _dp(c), omega, C.byref(part),
+                         C.byref(options) if options is not None else None))
+    return h
+
+
+def dd3_destroy(h):
+    load().dd3_destroy(h)
+
+
+def dd3_sizes(h):
+    v = [C.c_int64() for _ in range(4)]
+    _check(load().dd3_sizes(h, *[C.byref(x) for x in v]))
+    return dict(zip(["n_global", "n_local", "n_sub", "n_iface"], [x.value for x in v]))
+
+
+def dd3_time_steps(h):
+    n = dd3_sizes(h)["n_sub"]
+    out = (C.c_int * n)()
+    _check(load().dd3_time_steps(h, out))
+    return np.array(out[:], dtype=np.int64)
+
+
+def dd3_mesh_coords(nx, ny, nz, degree, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, z0=-1.0, z1=1.0):
+    """Global GLL node coordinates of a box (no handle)."""
+    box = dd_box(x0, x1, y0, y1, z0, z1, nx, ny, nz)
+    n = (nx * degree + 1) * (ny * degree + 1) * (nz * degree + 1)
+    x, y, z = np.empty(n), np.empty(n), np.empty(n)
+    _check(load().dd3_mesh_coords(C.byref(box), degree, _dp(x), _dp(y), _dp(z)))
+    return x, y, z
+
+
+def dd3_sweep(h, g_in=None, f=None, src=1.0, want_u=True):
+    """One DD cycle on the box; g_in complex in the g layout (None = 0).
+    Returns (g_out, u_sub, wh_iters)."""
+    s = dd3_sizes(h)
+    g_re = g_im = None
+    if g_in is not None:
+        g_in = np.asarray(g_in, dtype=complex)
+        g_re, g_im = _f64(g_in.real), _f64(g_in.imag)
+    f_re = f_im = None
+    if f is not None:
+        f = np.asarray(f)
+        f_re = _f64(f.real)
+        f_im = _f64(f.imag) if np.iscomplexobj(f) else None
+    go_re, go_im = np.empty(s["n_iface"]), np.empty(s["n_iface"])
+    nn = s["n_sub"] * s["n_local"]
+    u_re = np.empty(nn) if want_u else None
+    u_im = np.empty(nn) if want_u else None
+    its = (C.c_int * s["n_sub"])()
+    _check(load().dd3_sweep(h, _dp(g_re), _dp(g_im), _dp(f_re), _dp(f_im), src, _dp(go_re),
+                            _dp(go_im), _dp(u_re), _dp(u_im), its))
+    u = (u_re + 1j * u_im) if want_u else None
+    return go_re + 1j * go_im, u, np.array(its[:])
+
+
+def dd3_time_sweep(h, reps=10, fixed_iters=0):
+    ms, du = C.c_double(), C.c_double()
+    _check(load().dd3_time_sweep(h, reps, fixed_iters, C.byref(ms), C.byref(du)))
+    return ms.value, du.value
+
+
+def dd3_apply_operator_device(h, x, y, stream=None):
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(load().dd3_apply_operator_device(h, sp, C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(y.data_ptr())))

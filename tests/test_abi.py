@@ -1,5 +1,5 @@
 """CPU checks of the C ABI: the library loads, exports every entry point
-that include/wavedd.h declares, and rejects bad arguments before any device
+that include/wavedd.h and include/wavedd3.h declare, and rejects bad arguments before any device
 work (no GPU needed)."""
 import ctypes as C
 import os
@@ -11,12 +11,12 @@ import pytest
 from paper_2606_21695_amd import wavedd
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "wavedd.h")
+HEADERS = [os.path.join(ROOT, "include", "wavedd.h"), os.path.join(ROOT, "include", "wavedd3.h")]
 
 
 def declared():
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(dd_\w+)\s*\(", txt, re.M)))
+    txt = "\n".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(dd3?_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_lists_binding_exports():
@@ -161,8 +161,8 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {name: getattr(wavedd, name) for name in
                ("dd_mesh", "dd_partition", "dd_options", "dd_stats", "dd_problem",
-                "dd_engine_info")}
-    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wavedd.h"', "int main(void) {"]
+                "dd_engine_info", "dd_box", "dd_partition3")}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wavedd3.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
         for fname, _ in cls._fields_:
@@ -182,3 +182,49 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(name, "size")] == ctypes.sizeof(cls), name
         for fname, _ in cls._fields_:
             assert got[(name, fname)] == getattr(cls, fname).offset, (name, fname)
+
+
+def _box_setup(**kw):
+    a = dict(nx=4, ny=4, nz=4, degree=2, omega=6.0, sx=2, sy=2, sz=2)
+    a.update(kw)
+    N = (a["nx"] * a["degree"] + 1) * (a["ny"] * a["degree"] + 1) * (a["nz"] * a["degree"] + 1)
+    c = a.pop("c", np.ones(N))
+    return wavedd.dd3_setup(a["nx"], a["ny"], a["nz"], a["degree"], c, a["omega"], a["sx"],
+                            a["sy"], a["sz"])
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(sx=3), "does not divide"),
+    (dict(degree=5), "degree"),
+    (dict(omega=-1.0), "omega"),
+    (dict(nx=0), "empty"),
+    (dict(nx=8, ny=8, nz=8, degree=3, sx=2, sy=2, sz=2), "exceeds 1024"),
+])
+def test_box_setup_rejects_bad_arguments(kw, needle):
+    with pytest.raises(wavedd.WaveddError) as ei:
+        _box_setup(**kw)
+    assert ei.value.code == wavedd.DD_EINVAL
+    assert needle in str(ei.value)
+
+
+def test_box_setup_rejects_nonpositive_wavespeed():
+    c = np.ones(9 ** 3)
+    c[17] = 0.0
+    with pytest.raises(wavedd.WaveddError) as ei:
+        _box_setup(c=c)
+    assert ei.value.code == wavedd.DD_EINVAL and "wavespeed[17]" in str(ei.value)
+
+
+def test_box_null_handle_calls_fail_cleanly():
+    lib = wavedd.load()
+    assert lib.dd3_sizes(None, None, None, None, None) == wavedd.DD_EINVAL
+    assert lib.dd3_time_sweep(None, 1, 1, None, None) == wavedd.DD_EINVAL
+    lib.dd3_destroy(None)
+
+
+def test_box_mesh_coords_match_oracle():
+    from oracle import sem3
+    for (nx, ny, nz, P) in [(2, 3, 2, 3), (1, 1, 4, 1), (3, 2, 2, 4)]:
+        x, y, z = wavedd.dd3_mesh_coords(nx, ny, nz, P, -1.0, 2.0, 0.0, 1.0, -0.5, 0.5)
+        X, Y, Z = sem3.node_coords(sem3.Box(nx, ny, nz, P, -1.0, 2.0, 0.0, 1.0, -0.5, 0.5))
+        assert max(np.abs(x - X).max(), np.abs(y - Y).max(), np.abs(z - Z).max()) < 1e-14
