@@ -13,6 +13,8 @@ on the host CPU on a bounded sample of the same workload.
                     [--precision fp64|fp32] [--no-cpu]
     python bench.py --config c4      batched solves of 400 subdomains
     python bench.py --serve          serving engine on a Poisson request stream
+    python bench.py --config c6      box (3D) DD cycle of 5 WaveHoltz iterations
+                                     against the whole-box operator
 """
 import argparse
 import json
@@ -351,6 +353,73 @@ def operator_ms(W, h, reps=50):
     return e0.elapsed_time(e1) / reps
 
 
+def flops_per_update3(P):
+    """Algorithmic FLOP of one box DOF-update: the three (2P+1)-point
+    stiffness windows with one merged centre tap 2(6P+1), p update 2,
+    velocity update 6, filter 4."""
+    return 2 * (6 * P + 1) + 12
+
+
+def box_bench(args):
+    """Box (3D) workloads: the DD cycle of the paper's 3D timing (every
+    subdomain runs exactly 5 WaveHoltz iterations from random complex
+    interface data, one launch) against one whole-box operator
+    evaluation."""
+    import torch
+    import workloads
+    from paper_2606_21695_amd import wavedd as W
+    W.require_gpu()
+    torch.cuda.set_device(0)
+    wl = workloads.CONFIGS3[args.config]()
+    prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
+    X, Y, Z = W.dd3_mesh_coords(wl.nx, wl.ny, wl.nz, wl.P, *wl.box)
+    o = W.dd_default_options(precision=prec, tau_in=0.0, max_wh=5)
+    h = W.dd3_setup(wl.nx, wl.ny, wl.nz, wl.P, wl.c(X, Y, Z), wl.omega, wl.sx, wl.sy, wl.sz,
+                    *wl.box, options=o)
+    s = W.dd3_sizes(h)
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(s["n_iface"]) + 1j * rng.standard_normal(s["n_iface"])
+    # the timed launches start from this random interface state
+    W.dd3_sweep(h, g, None, 0.0, want_u=False)
+    log(f"{args.config}: {s['n_sub']} subdomains of {s['n_local']} nodes, timing")
+    ms, dof = W.dd3_time_sweep(h, args.steps, 5)
+    n = s["n_global"]
+    x = torch.randn(2 * n, dtype=torch.float64, device="cuda",
+                 generator=torch.Generator(device="cuda").manual_seed(0))
+    y = torch.empty_like(x)
+    st = torch.cuda.Stream()
+    for _ in range(3):
+        W.dd3_apply_operator_device(h, x, y, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(50):
+        W.dd3_apply_operator_device(h, x, y, st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    op_ms = e0.elapsed_time(e1) / 50
+    nt = W.dd3_time_steps(h)
+    W.dd3_destroy(h)
+    flop = flops_per_update3(wl.P) * dof
+    peak = PEAK_TFLOPS[args.precision]
+    ach = flop / (ms * 1e-3) / 1e12
+    out = {"metric": "WaveHoltz DOF-updates/s (box DD cycle, 5 WaveHoltz iterations, random input)",
+           "value": dof / (ms * 1e-3), "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision.replace("fp", "f"),
+           "data": "synthetic (random complex interface data)",
+           "config": {"workload": f"{args.config}: {wl.nx}x{wl.ny}x{wl.nz} elements P={wl.P}, "
+                                  f"{wl.sx}x{wl.sy}x{wl.sz} subdomains of {s['n_local']} nodes, "
+                                  f"c=1 on [-1,1]^3, omega={wl.omega:.2f}, N_t={int(nt.max())}",
+                      "kernel": "sweep3_kernel"},
+           "dof_updates_per_launch": dof,
+           "operator_ms": op_ms, "dd_cycle_over_operator": ms / op_ms,
+           "operator_gbs": 48.0 * n / (op_ms * 1e-3) / 1e9,
+           "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                        "frac": ach / peak, "traffic": None, "kernel": "sweep3_kernel"}}
+    print(json.dumps(out))
+
+
 def protocol_bench(args):
     """The paper's DD-cycle timing (Sec. VII-A): sweeps of exactly 5
     WaveHoltz iterations per subdomain from random complex interface data,
@@ -480,6 +549,8 @@ def main():
         args.max_wh = 100 if args.config in ("c1", "c2", "c2_small", "c2_t1") and not args.serve else 1000
     if args.serve:
         return serve_bench(args)
+    if args.config.startswith("c6"):
+        return box_bench(args)
     if args.protocol:
         return protocol_bench(args)
     if args.config == "c4":

@@ -241,47 +241,69 @@ __global__ void __launch_bounds__(kMaxWG) sweep3_kernel(const Sweep3Args<Real> A
     }
 }
 
-// y = S x on the whole box: one thread per node, blocks along grid rows.
+// y = S x on the whole box.  A workgroup owns a 64 x 4 tile of (x, y)
+// columns and marches along z over a chunk of planes: each thread keeps the
+// 2P+1 values of its column around the current plane in registers (the z
+// taps), and takes the x and y taps from the cache (neighbours in the tile
+// or in the tiles beside it, read in the same plane step), so x is fetched
+// from HBM about once.  Tiles are numbered so that the workgroups the
+// hardware places on one XCD (every eighth) hold a contiguous range of
+// tiles: tiles side by side in y then share that XCD's L2.
+constexpr int kOpTX = 64, kOpTY = 4;
+
 template <int P>
-__global__ void __launch_bounds__(256) operator3_kernel(const Operator3Args A, const double2* x,
-                                                        double2* y) {
-    const int bpr = (A.Nx + 255) / 256;
-    const int row = (int)blockIdx.x / bpr;
-    const int i = ((int)blockIdx.x - row * bpr) * 256 + (int)threadIdx.x;
-    if (i >= A.Nx) return;
-    const int j = row % A.Ny, k = row / A.Ny;
+__global__ void __launch_bounds__(kOpTX * kOpTY) operator3_kernel(const Operator3Args A,
+                                                                  const double2* x, double2* y) {
+    constexpr int W = 2 * P + 1;
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int nbx = (A.Nx + kOpTX - 1) / kOpTX, nby = (A.Ny + kOpTY - 1) / kOpTY;
+    const int bx = t % nbx, by = (t / nbx) % nby, kc = t / (nbx * nby);
+    const int i = bx * kOpTX + (int)(threadIdx.x % kOpTX);
+    const int j = by * kOpTY + (int)(threadIdx.x / kOpTX);
+    const int k0 = kc * A.kchunk, k1 = min(A.Nz, k0 + A.kchunk);
+    if (i >= A.Nx || j >= A.Ny || k0 >= k1) return;
     const int64_t sj = A.Nx, sk = (int64_t)A.Nx * A.Ny;
-    const int64_t g = (int64_t)k * sk + (int64_t)j * sj + i;
-    double wx[2 * P + 1], wy[2 * P + 1], wz[2 * P + 1];
+    double wx[W], wy[W];
     window3<double, P>(wx, i, A.nx, A.K1);
     window3<double, P>(wy, j, A.ny, A.K1);
-    window3<double, P>(wz, k, A.nz, A.K1);
-    double2 X = make_double2(0.0, 0.0), Y = X, Z = X;
+    const double wxi = A.wx[i], wyj = A.wy[j];
+    const int64_t col = (int64_t)j * sj + i;
+    // z window: zw[P + d] = x at plane k + d (0 off the box)
+    double2 zw[W];
 #pragma unroll
-    for (int t = 0; t <= 2 * P; ++t) {
-        const int di = t - P;
-        if (i + di >= 0 && i + di < A.Nx) {
-            const double2 v = x[g + di];
-            X.x += wx[t] * v.x;
-            X.y += wx[t] * v.y;
-        }
-        if (j + di >= 0 && j + di < A.Ny) {
-            const double2 v = x[g + di * sj];
-            Y.x += wy[t] * v.x;
-            Y.y += wy[t] * v.y;
-        }
-        if (k + di >= 0 && k + di < A.Nz) {
-            const double2 v = x[g + di * sk];
-            Z.x += wz[t] * v.x;
-            Z.y += wz[t] * v.y;
-        }
+    for (int d = -P; d <= P; ++d) {
+        const int kk = k0 + d;
+        zw[P + d] = (kk >= 0 && kk < A.Nz && d < P) ? x[kk * sk + col] : make_double2(0.0, 0.0);
     }
-    const double cx = A.sx_ref * A.wy[j] * A.wz[k], cy = A.sy_ref * A.wx[i] * A.wz[k];
-    const double cz = A.sz_ref * A.wx[i] * A.wy[j];
-    const double2 v = x[g];
-    const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
-    y[g] = make_double2(cx * X.x + cy * Y.x + cz * Z.x - m * v.x + h * v.y,
-                        cx * X.y + cy * Y.y + cz * Z.y - m * v.y - h * v.x);
+    for (int k = k0; k < k1; ++k) {
+        if (k + P < A.Nz) zw[W - 1] = x[(k + P) * sk + col];
+        const int64_t g = k * sk + col;
+        double wz[W];
+        window3<double, P>(wz, k, A.nz, A.K1);
+        double2 X = make_double2(0.0, 0.0), Y = X, Z = X;
+#pragma unroll
+        for (int tt = 0; tt < W; ++tt) {
+            const int d = tt - P;
+            const double2 vx = (i + d >= 0 && i + d < A.Nx) ? x[g + d] : make_double2(0.0, 0.0);
+            const double2 vy = (j + d >= 0 && j + d < A.Ny) ? x[g + d * sj] : make_double2(0.0, 0.0);
+            X.x += wx[tt] * vx.x;
+            X.y += wx[tt] * vx.y;
+            Y.x += wy[tt] * vy.x;
+            Y.y += wy[tt] * vy.y;
+            Z.x += wz[tt] * zw[tt].x;
+            Z.y += wz[tt] * zw[tt].y;
+        }
+        const double wzk = A.wz[k];
+        const double cx = A.sx_ref * wyj * wzk, cy = A.sy_ref * wxi * wzk, cz = A.sz_ref * wxi * wyj;
+        const double2 v = zw[P];
+        const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
+        y[g] = make_double2(cx * X.x + cy * Y.x + cz * Z.x - m * v.x + h * v.y,
+                            cx * X.y + cy * Y.y + cz * Z.y - m * v.y - h * v.x);
+#pragma unroll
+        for (int d = 0; d < W - 1; ++d) zw[d] = zw[d + 1];
+        zw[W - 1] = make_double2(0.0, 0.0);
+    }
 }
 
 }  // namespace
@@ -307,8 +329,10 @@ hipError_t launch_sweep3(const Sweep3Args<Real>& a, int wg, hipStream_t s) {
 }
 
 hipError_t launch_operator3(const Operator3Args& a, const double2* x, double2* y, hipStream_t s) {
-    const unsigned blocks = (unsigned)(((a.Nx + 255) / 256) * (int64_t)a.Ny * a.Nz);
-#define L(PP) hipLaunchKernelGGL((operator3_kernel<PP>), dim3(blocks), dim3(256), 0, s, a, x, y)
+    const int64_t tiles = (int64_t)((a.Nx + kOpTX - 1) / kOpTX) * ((a.Ny + kOpTY - 1) / kOpTY);
+    const int64_t nkc = (a.Nz + a.kchunk - 1) / a.kchunk;
+    const unsigned blocks = (unsigned)(tiles * nkc);
+#define L(PP) hipLaunchKernelGGL((operator3_kernel<PP>), dim3(blocks), dim3(kOpTX * kOpTY), 0, s, a, x, y)
     switch (a.P) {
         case 1: L(1); break;
         case 2: L(2); break;

@@ -3129,6 +3129,12 @@ int dd3_apply_operator_device(dd3_handle* h, void* stream, const double* d_x, do
     a.nx = h->box.nx;
     a.ny = h->box.ny;
     a.nz = h->box.nz;
+    // z chunks: enough workgroups to fill the chip (about 2048), chunks of
+    // at least 4P planes so the 2P-plane warm-up of the z window stays small
+    const int64_t tiles = (int64_t)((h->Nx + 63) / 64) * ((h->Ny + 3) / 4);
+    const int64_t nkc = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles,
+                                                               h->Nz / (4 * h->P)));
+    a.kchunk = (int)((h->Nz + nkc - 1) / nkc);
     a.sx_ref = 2.0 / h->hx;
     a.sy_ref = 2.0 / h->hy;
     a.sz_ref = 2.0 / h->hz;

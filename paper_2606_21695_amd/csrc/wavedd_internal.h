@@ -206,6 +206,7 @@ size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t rea
 // Whole-box operator y = S x (FP64) on the global node grid.
 struct Operator3Args {
     int Nx, Ny, Nz, P, nx, ny, nz;
+    int kchunk;                     // planes per workgroup along z
     double sx_ref, sy_ref, sz_ref;  // 2/hx, 2/hy, 2/hz
     const double* wx;               // assembled physical 1D weights (Nx, Ny, Nz)
     const double* wy;

@@ -141,13 +141,13 @@ def test_sweep_is_deterministic(gpu_lib):
 
 
 @pytest.mark.parametrize("nx,ny,nz,P", [(3, 4, 5, 3), (20, 6, 3, 2), (70, 3, 2, 1),
-                                        (4, 3, 3, 4)])
+                                        (4, 3, 3, 4), (20, 4, 40, 3)])
 def test_operator(gpu_lib, nx, ny, nz, P):
-    """Whole-box S x against the oracle's assembled S, on grids whose rows
-    span several 256-thread blocks."""
+    """Whole-box S x against the oracle's assembled S: ragged 64 x 4 column
+    tiles, several z chunks (the last shape: 40 workgroups, so the XCD tile
+    numbering is active)."""
     import torch
     W = gpu_lib
-    shape = (nx, ny, nz, P, 1, 1, 1)
     X, Y, Z = W.dd3_mesh_coords(nx, ny, nz, P, *BOX)
     o = W.dd_default_options()
     # one subdomain may exceed the sweep's 1024-node limit: set up with a
@@ -167,7 +167,6 @@ def test_operator(gpu_lib, nx, ny, nz, P):
     y = y[0::2] + 1j * y[1::2]
     ref = S @ x
     assert np.linalg.norm(y - ref) < 1e-13 * np.linalg.norm(ref)
-    del shape
 
 
 def test_time_sweep_reports_dof_updates(gpu_lib):
@@ -180,3 +179,82 @@ def test_time_sweep_reports_dof_updates(gpu_lib):
     W.dd3_destroy(h)
     assert ms > 0
     assert du == pytest.approx(float(np.sum(s["n_local"] * (nt - 1) * 5)))
+
+
+def _box_workload_setup(W, wl, prec, m):
+    X, Y, Z = W.dd3_mesh_coords(wl.nx, wl.ny, wl.nz, wl.P, *wl.box)
+    o = W.dd_default_options(precision=prec, tau_in=0.0, max_wh=m)
+    h = W.dd3_setup(wl.nx, wl.ny, wl.nz, wl.P, wl.c(X, Y, Z), wl.omega, wl.sx, wl.sy, wl.sz,
+                    *wl.box, options=o)
+    return h, X, Y, Z
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c6_small_protocol_sweep(gpu_lib, prec):
+    """The c6 subdomain shape (2^3 elements, P=3, 343 nodes) at 8^3 elements:
+    one DD cycle of the paper's 5 WaveHoltz iterations against the oracle."""
+    import workloads
+    W = gpu_lib
+    wl = workloads.c6_small()
+    h, Xl, Yl, Zl = _box_workload_setup(W, wl, prec, 5)
+    mesh = sem3.Box(wl.nx, wl.ny, wl.nz, wl.P, *wl.box)
+    X, Y, Z = sem3.node_coords(mesh)
+    dec = dd3.Decomposition3(mesh, dd3.Partition3(wl.sx, wl.sy, wl.sz), wl.c(X, Y, Z), wl.omega)
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal(dec.n_if) + 1j * rng.standard_normal(dec.n_if)
+    g_gpu, u_gpu, its = W.dd3_sweep(h, g, wl.f(Xl, Yl, Zl), 1.0)
+    W.dd3_destroy(h)
+    g_ref, u_ref = dec.sweep(g, wl.f(X, Y, Z), 1.0, wh.make_solver(dec, fixed_iters=5))
+    assert (its == 5).all()
+    tol = 1e-11 if prec == 0 else 1e-4
+    assert _rel([u_gpu], u_ref) < tol
+    assert _rel([g_gpu], [g_ref]) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c6_full_size_sweep_sampled(gpu_lib, prec):
+    """The full c6 launch (64^3 elements, 32768 subdomains, the bench's
+    configuration) checked on sampled subdomains: each sampled subdomain's
+    WaveHoltz iterate equals the oracle's on that subdomain alone (a
+    one-subdomain decomposition of its box with its slice of g), and the
+    interface data it sends to every neighbour equals -g - 2i(omega/c)u."""
+    import workloads
+    W = gpu_lib
+    wl = workloads.c6()
+    h, Xl, Yl, Zl = _box_workload_setup(W, wl, prec, 5)
+    s = W.dd3_sizes(h)
+    rng = np.random.default_rng(66)
+    g = rng.standard_normal(s["n_iface"]) + 1j * rng.standard_normal(s["n_iface"])
+    print(f"c6 full-size sweep prec={prec}", flush=True)
+    g_gpu, u_gpu, its = W.dd3_sweep(h, g, wl.f(Xl, Yl, Zl), 1.0)
+    W.dd3_destroy(h)
+    assert (its == 5).all()
+    P, L, nloc, per = wl.P, s["n_sub"], s["n_local"], s["n_iface"] // s["n_sub"]
+    mx, my, mz = wl.nx // wl.sx, wl.ny // wl.sy, wl.nz // wl.sz
+    hx = (wl.box[1] - wl.box[0]) / wl.nx
+    hy = (wl.box[3] - wl.box[2]) / wl.ny
+    hz = (wl.box[5] - wl.box[4]) / wl.nz
+    tol = 1e-11 if prec == 0 else 1e-4
+    for l in (0, L // 2 + 17 * wl.sx + 5, L - 1):
+        a, b, c = l % wl.sx, (l // wl.sx) % wl.sy, l // (wl.sx * wl.sy)
+        x0, y0, z0 = wl.box[0] + a * mx * hx, wl.box[2] + b * my * hy, wl.box[4] + c * mz * hz
+        sub = sem3.Box(mx, my, mz, P, x0, x0 + mx * hx, y0, y0 + my * hy, z0, z0 + mz * hz)
+        X, Y, Z = sem3.node_coords(sub)
+        one = dd3.Decomposition3(sub, dd3.Partition3(1, 1, 1), wl.c(X, Y, Z), wl.omega)
+        gl = g[l * per:(l + 1) * per]
+        b_l = one.rhs(0, wl.f(X, Y, Z), gl, 1.0)
+        u_ref = wh.make_solver(one, fixed_iters=5)(0, b_l)
+        u_l = u_gpu[l * nloc:(l + 1) * nloc]
+        assert _rel([u_l], [u_ref]) < tol, l
+        for face in range(6):
+            step = dd3.STEP[face]
+            a2, b2, c2 = a + step[0], b + step[1], c + step[2]
+            if not (0 <= a2 < wl.sx and 0 <= b2 < wl.sy and 0 <= c2 < wl.sz):
+                continue
+            r = (c2 * wl.sy + b2) * wl.sx + a2
+            o2 = one.face_off[dd3.OPPOSITE[face]]
+            nodes = one.local_faces[face]
+            sent = g_gpu[r * per + o2:r * per + o2 + one.face_len[face]]
+            want = (-gl[one.face_off[face]:one.face_off[face] + one.face_len[face]]
+                    - 2j * (wl.omega / one.subs[0]["c"][nodes]) * u_ref[nodes])
+            assert _rel([sent], [want]) < tol, (l, face)

@@ -24,6 +24,15 @@ follow those shapes:
           elements per side, P in 1..4) total 400, log-normal smooth
           wavespeed with contrast up to 3, omega=40.
 * ``c5``  a seeded Poisson-arrival stream of independent solves.
+
+Box (3D) workloads, the paper's second benchmark family (constant c on
+[-1,1]^3, uniform hexahedra, 16^3 to 128^3 elements, degree up to 3):
+
+* ``c6``     64^3 elements, P=3, 32^3 subdomains of 2^3 elements (343 nodes),
+             c=1, omega for 10 points per wavelength, Gaussian source.
+* ``c6_p1``  128^3 elements, P=1, 16^3 subdomains of 8^3 elements (729 nodes).
+* ``c6_small`` 8^3 elements, P=3, 4^3 subdomains of 2^3 elements: the ``c6``
+             subdomain shape at a size the oracle finishes in seconds.
 """
 from dataclasses import dataclass, field
 from typing import Callable, Optional
@@ -228,3 +237,52 @@ def c5(seed=5, n_requests=2000):
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c2_small": c2_small, "c2_t1": c2_t1, "c3": c3}
+
+
+@dataclass
+class Workload3:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    P: int
+    sx: int
+    sy: int
+    sz: int
+    omega: float
+    c: Callable            # c(X, Y, Z)
+    f: Callable            # f(X, Y, Z)
+    box: tuple = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
+
+
+def constant3(val):
+    def c(X, Y, Z):
+        return np.full(np.shape(X), float(val))
+    return c
+
+
+def gaussian3(x0, y0, z0, sigma):
+    def f(X, Y, Z):
+        return np.exp(-((X - x0) ** 2 + (Y - y0) ** 2 + (Z - z0) ** 2) / (2 * sigma ** 2))
+    return f
+
+
+def _box(name, n, P, sub):
+    om = _omega_ppw(P, 2.0 / n, 1.0, 10.0)
+    return Workload3(name, n, n, n, P, n // sub, n // sub, n // sub, om, constant3(1.0),
+                     gaussian3(0.1, -0.2, 0.15, 0.1))
+
+
+def c6():
+    return _box("c6", 64, 3, 2)
+
+
+def c6_p1():
+    return _box("c6_p1", 128, 1, 8)
+
+
+def c6_small():
+    return _box("c6_small", 8, 3, 2)
+
+
+CONFIGS3 = {"c6": c6, "c6_p1": c6_p1, "c6_small": c6_small}
