@@ -10,6 +10,8 @@
 // with beta into the per-node coefficients bX, bY, bZ.
 #include "wavedd_internal.h"
 
+#include <vector>
+
 namespace wdd {
 
 namespace {
@@ -82,7 +84,9 @@ __device__ void sweep3_item(const Sweep3Args<Real>& A, const Sub3& d, int item, 
     }
     const int nloc = nxl * nyl * nzl;
     const bool has = tid < nloc;
-    const int t0 = has ? tid : 0;
+    // node of this thread: a permutation that gives the lanes of each group
+    // distinct LDS banks (every tap is a fixed offset from the node's slot)
+    const int t0 = has ? A.perm[tid] : 0;
     const int il = t0 % nxl, jl = (t0 / nxl) % nyl, kl = t0 / (nxl * nyl);
     const int pidx = ((kl + P) * py + (jl + P)) * px + (il + P);
     const int sy = px, sz = px * py;
@@ -310,6 +314,45 @@ __global__ void __launch_bounds__(kOpTX * kOpTY) operator3_kernel(const Operator
 
 size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t real_size) {
     return 40 * sizeof(double) + ((size_t)box_tab_off(nxl, nyl, nzl, P) + 4 * (size_t)nt_max) * real_size;
+}
+
+void sweep3_thread_order(int nxl, int nyl, int nzl, int P, size_t real_size, int* perm) {
+    // LDS slot of node (il, jl, kl) in the padded grid, as in the kernel;
+    // nodes are bucketed by slot mod G and each group of G lanes takes one
+    // node per residue, lane j of the group the residue j (so each half of
+    // the group also has distinct residues mod G/2); shifting every slot by a
+    // tap offset keeps the residues of a group distinct.
+    const int G = (int)(256 / real_size);
+    const int px = nxl + 2 * P, py = nyl + 2 * P;
+    const int n = nxl * nyl * nzl;
+    std::vector<std::vector<int>> bucket(G);
+    for (int t = n - 1; t >= 0; --t) {
+        const int il = t % nxl, jl = (t / nxl) % nyl, kl = t / (nxl * nyl);
+        const int slot = ((kl + P) * py + (jl + P)) * px + (il + P);
+        bucket[slot % G].push_back(t);
+    }
+    int filled = 0;
+    std::vector<int> rest;
+    while (filled < n) {
+        int full = 1;
+        for (int r = 0; r < G; ++r)
+            if (bucket[r].empty()) full = 0;
+        if (!full) break;
+        for (int r = 0; r < G; ++r) {
+            perm[filled++] = bucket[r].back();
+            bucket[r].pop_back();
+        }
+    }
+    // the remainder: round-robin over the residues still present
+    for (bool any = true; any;) {
+        any = false;
+        for (int r = 0; r < G; ++r)
+            if (!bucket[r].empty()) {
+                perm[filled++] = bucket[r].back();
+                bucket[r].pop_back();
+                any = true;
+            }
+    }
 }
 
 template <typename Real>

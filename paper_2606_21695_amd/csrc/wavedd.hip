@@ -2614,7 +2614,7 @@ struct dd3_handle {
     DBuf<unsigned char> d_tab;   // kap, kaph, cs, sn (Real, tab_len each)
     DBuf<double> d_w1d, d_kside, d_wx, d_wy, d_wz, d_M, d_H, d_f;
     DBuf<double2> d_gin, d_gout, d_u;
-    DBuf<int> d_iters;
+    DBuf<int> d_iters, d_perm;
     bool has_f = false;
 };
 
@@ -2631,6 +2631,7 @@ void dd3_free(dd3_handle* h) {
     h->d_gout.free();
     h->d_u.free();
     h->d_iters.free();
+    h->d_perm.free();
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -2892,6 +2893,18 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
     HIPCHK(h->d_gout.alloc(h->n_if));
     HIPCHK(h->d_u.alloc(nn));
     HIPCHK(h->d_iters.alloc(L));
+    HIPCHK(h->d_perm.alloc(nloc));
+    {
+        std::vector<int> perm(nloc);
+        wdd::sweep3_thread_order(nxl, nyl, nzl, P, rs, perm.data());
+        std::vector<char> seen(nloc, 0);
+        for (int64_t t = 0; t < nloc; ++t) {
+            if (perm[t] < 0 || perm[t] >= nloc || seen[perm[t]])
+                return fail(DD_EINVAL, "internal: thread order is not a permutation");
+            seen[perm[t]] = 1;
+        }
+        HIPCHK(hipMemcpy(h->d_perm.p, perm.data(), sizeof(int) * nloc, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(h->d_desc.p, h->desc.data(), sizeof(wdd::Sub3) * L, hipMemcpyHostToDevice));
     const std::vector<double>* coefs[5] = {&alpha, &bX, &bY, &bZ, &beta};
     for (int i = 0; i < 5; ++i) CHK(upload_as(h, h->d_coef.p + i * nn * rs, *coefs[i]));
@@ -2930,6 +2943,7 @@ wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, double src, bool with_f, 
     a.mz = h->mz;
     a.P = h->P;
     a.per_sub = (int)h->per_sub;
+    a.perm = h->d_perm.p;
     for (int s = 0; s < 6; ++s) a.face_off[s] = h->face_off[s];
     a.alpha = coef;
     a.betaX = coef + nn;

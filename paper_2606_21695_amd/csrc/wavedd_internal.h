@@ -174,6 +174,7 @@ struct Sweep3Args {
     int n_items;
     int nxl, nyl, nzl, mx, my, mz, P;
     int per_sub;             // interface slots per subdomain
+    const int* perm;         // thread -> local node (nloc entries, shared by all subdomains)
     int face_off[6];         // first slot of each face within a subdomain
     const Real* alpha;       // (M - theta H) / (M + theta H)
     const Real* betaX;       // beta * (2/hx) * Wy * Wz
@@ -202,6 +203,10 @@ struct Sweep3Args {
 template <typename Real>
 hipError_t launch_sweep3(const Sweep3Args<Real>& a, int wg, hipStream_t s);
 size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t real_size);
+// Thread -> node order of the 3D sweep for a subdomain shape and sweep
+// precision: each aligned group of 256 / real_size lanes reads distinct LDS
+// banks in every stencil tap where the shape allows.
+void sweep3_thread_order(int nxl, int nyl, int nzl, int P, size_t real_size, int* perm);
 
 // Whole-box operator y = S x (FP64) on the global node grid.
 struct Operator3Args {
