@@ -39,6 +39,13 @@ MEASURED_TRAFFIC = {
     ("d577db17b639aa2c", "protocol", "c3", "fp32"): round((28815929.2 * 2.0 + 31884724.0) * 1024),
 }
 
+# HBM bytes per launch of the box (3D) sweep kernel, same counters and scale,
+# keyed by the hash of the box kernel source (comments ignored).
+MEASURED_TRAFFIC3 = {
+    ("d62ef9d7610971a1", "c6", "fp64"): round((418575.0 * 2.0 + 331907.2) * 1024),
+    ("d62ef9d7610971a1", "c6", "fp32"): round((332785.8 * 2.0 + 333685.0) * 1024),
+}
+
 # section markers of each layout in the kernel source
 _SECTIONS = {1: ("// NODE layout (one DOF per thread)", "// STREAM layout"),
              2: ("// PATCH layout, one barrier per step", "// NODE layout (one DOF per thread)"),
@@ -62,6 +69,15 @@ def kernel_hash(layout, src=None):
     i = src.index(a)
     body = src[i:src.index(b, i + len(a))]
     code = [re.sub(r"//.*$", "", line).rstrip() for line in (head + body).splitlines()]
+    return hashlib.sha256("\n".join(x for x in code if x).encode()).hexdigest()[:16]
+
+
+def kernel3_hash():
+    """Hash of the box sweep kernel source (comments and blank lines dropped)."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_2606_21695_amd", "csrc", "sweep3_kernels.hip")).read()
+    code = [re.sub(r"//.*$", "", line).rstrip() for line in src.splitlines()]
     return hashlib.sha256("\n".join(x for x in code if x).encode()).hexdigest()[:16]
 
 
@@ -416,7 +432,9 @@ def box_bench(args):
            "operator_ms": op_ms, "dd_cycle_over_operator": ms / op_ms,
            "operator_gbs": 48.0 * n / (op_ms * 1e-3) / 1e9,
            "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                        "frac": ach / peak, "traffic": None, "kernel": "sweep3_kernel"}}
+                        "frac": ach / peak, "kernel": "sweep3_kernel",
+                        "traffic": MEASURED_TRAFFIC3.get((kernel3_hash(), args.config,
+                                                         args.precision))}}
     print(json.dumps(out))
 
 
