@@ -29,9 +29,10 @@
  *   Slots on the outer boundary carry physical impedance data; the sweep
  *   writes 0 there.
  *
- * Options: dd_options from wavedd.h; precision, tau_in, max_wh, cfl and
- * nt_override are used (tau_in <= 0 runs exactly max_wh WaveHoltz
- * iterations), the outer-solver, layout, warm-start and tc2 fields are
+ * Options: dd_options from wavedd.h; precision, tau_in, max_wh, cfl,
+ * nt_override and restart are used (tau_in <= 0 runs exactly max_wh
+ * WaveHoltz iterations); the outer method is always GMRES without
+ * refinement, and the layout, refine, relax, warm-start and tc2 fields are
  * ignored.  Errors, threading and memory ownership as in wavedd.h.
  */
 #ifndef WAVEDD3_H
@@ -92,6 +93,26 @@ int dd3_sweep(dd3_handle* h, const double* g_re, const double* g_im, const doubl
  * launches after one warm-up and the DOF-updates of one launch
  * (sum of nloc*(N_t-1)*iterations; may be NULL). */
 int dd3_time_sweep(dd3_handle* h, int reps, int fixed_iters, double* ms, double* dof_updates);
+
+/* Solve the box problem (f: N values at the global nodes, f_im may be
+ * NULL; no outer boundary data): restarted GMRES (dd_options.restart) in
+ * FP64 on (I - T) G = h over box sweeps (Sec. III last paragraph), T the
+ * sweep with sources off, h = sweep(0) with sources on, every sweep's
+ * WaveHoltz solves to tau_in (cap max_wh) in the handle's precision; then
+ * u from the sweep of the converged G, glued at the global nodes (mean of
+ * the subdomain copies).  u_re, u_im: N host values.  st (may be NULL):
+ * outer iterations, sweeps, rel_residual = max(GMRES estimate, true
+ * residual), true_rel_residual = ||h - (I - T) G|| / ||h|| from the final
+ * sweep, WaveHoltz totals, DOF-updates, seconds.  Returns DD_ENOTCONV
+ * (outputs written) when max_iter is reached first. */
+int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol, int max_iter,
+              double* u_re, double* u_im, dd_stats* st);
+
+/* Relative residual ||b - S u||_2 / ||b||_2 of the global box system
+ * eq. (4) in FP64, b = (f, phi), for a nodal u (host arrays; f_im may be
+ * NULL; f_re NULL means b = 0 and the result is ||S u||). */
+int dd3_residual(dd3_handle* h, const double* u_re, const double* u_im, const double* f_re,
+                 const double* f_im, double* rel);
 
 /* Whole-box operator y = S x = (A - i omega H - omega^2 M) x in FP64 on
  * device arrays (N complex, interleaved re/im), on `stream` (hipStream_t as

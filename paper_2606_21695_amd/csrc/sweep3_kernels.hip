@@ -310,6 +310,54 @@ __global__ void __launch_bounds__(kOpTX * kOpTY) operator3_kernel(const Operator
     }
 }
 
+// Glue: every global node takes the mean of its subdomain copies (up to 8).
+__global__ void __launch_bounds__(256) glue3_kernel(const Operator3Args A, const double2* usub,
+                                                    int mx, int my, int mz, int sx, int sy, int sz,
+                                                    double2* ug) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t N = (int64_t)A.Nx * A.Ny * A.Nz;
+    if (g >= N) return;
+    const int i = (int)(g % A.Nx), j = (int)((g / A.Nx) % A.Ny), k = (int)(g / ((int64_t)A.Nx * A.Ny));
+    const int ex = mx * A.P, ey = my * A.P, ez = mz * A.P;
+    const int nxl = ex + 1, nyl = ey + 1, nzl = ez + 1;
+    const int64_t nloc = (int64_t)nxl * nyl * nzl;
+    const int a1 = min(i / ex, sx - 1), b1 = min(j / ey, sy - 1), c1 = min(k / ez, sz - 1);
+    const int a0 = (i == a1 * ex && a1 > 0) ? a1 - 1 : a1;
+    const int b0 = (j == b1 * ey && b1 > 0) ? b1 - 1 : b1;
+    const int c0 = (k == c1 * ez && c1 > 0) ? c1 - 1 : c1;
+    double sr = 0.0, si = 0.0;
+    int cnt = 0;
+    for (int c = c0; c <= c1; ++c)
+        for (int b = b0; b <= b1; ++b)
+            for (int a = a0; a <= a1; ++a) {
+                const int64_t l = ((int64_t)c * sy + b) * sx + a;
+                const int il = i - a * ex, jl = j - b * ey, kl = k - c * ez;
+                const double2 v = usub[l * nloc + ((int64_t)kl * nyl + jl) * nxl + il];
+                sr += v.x;
+                si += v.y;
+                ++cnt;
+            }
+    ug[g] = make_double2(sr / cnt, si / cnt);
+}
+
+// work[g] = (|b - Su|^2, |b|^2) with b = (f, phi) = vol * f (f may be null).
+__global__ void __launch_bounds__(256) residual3_kernel(const Operator3Args A, const double* f_re,
+                                                        const double* f_im, const double2* Su,
+                                                        double2* work) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t N = (int64_t)A.Nx * A.Ny * A.Nz;
+    if (g >= N) return;
+    const int i = (int)(g % A.Nx), j = (int)((g / A.Nx) % A.Ny), k = (int)(g / ((int64_t)A.Nx * A.Ny));
+    double br = 0.0, bi = 0.0;
+    if (f_re) {
+        const double vol = A.wx[i] * A.wy[j] * A.wz[k];
+        br = vol * f_re[g];
+        bi = f_im ? vol * f_im[g] : 0.0;
+    }
+    const double rr = br - Su[g].x, ri = bi - Su[g].y;
+    work[g] = make_double2(rr * rr + ri * ri, br * br + bi * bi);
+}
+
 }  // namespace
 
 size_t sweep3_lds_bytes(int nxl, int nyl, int nzl, int P, int nt_max, size_t real_size) {
@@ -384,6 +432,22 @@ hipError_t launch_operator3(const Operator3Args& a, const double2* x, double2* y
         default: return hipErrorInvalidValue;
     }
 #undef L
+    return hipGetLastError();
+}
+
+hipError_t launch_glue3(const Operator3Args& a, const double2* usub, int mx, int my, int mz, int sx,
+                        int sy, int sz, double2* ug, hipStream_t s) {
+    const int64_t N = (int64_t)a.Nx * a.Ny * a.Nz;
+    hipLaunchKernelGGL(glue3_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, usub,
+                       mx, my, mz, sx, sy, sz, ug);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual3(const Operator3Args& a, const double* f_re, const double* f_im,
+                            const double2* Su, double2* work, hipStream_t s) {
+    const int64_t N = (int64_t)a.Nx * a.Ny * a.Nz;
+    hipLaunchKernelGGL(residual3_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, f_re,
+                       f_im, Su, work);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -751,26 +752,64 @@ int run_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, boo
 
 // Hermitian inner products <V_i, w>, i < k, into host array out (device
 // reduction, one readback).
-int dots(dd_handle* h, const double2* V, int64_t ld, int k, const double2* w, cplx* out) {
-    HIPCHK(wdd::blas_multidot(h->blas, V, ld, k, w, h->n_if, h->stream));
-    std::vector<double2> tmp(k);
-    HIPCHK(hipMemcpyAsync(tmp.data(), h->blas.result, sizeof(double2) * k, hipMemcpyDeviceToHost,
-                          h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    for (int i = 0; i < k; ++i) out[i] = cplx(tmp[i].x, tmp[i].y);
+// Device vectors and operator of one restarted GMRES run: the outer
+// iteration's Krylov method, shared by the 2D and box handles.
+struct Krylov {
+    wdd::Blas* blas;
+    hipStream_t stream;
+    int64_t n, ld;                 // vector length, basis stride
+    int m;                         // restart length
+    double2 *V, *r, *coefs;        // basis [(m+1) * ld], residual [n], combination [m+1]
+    std::function<int(const double2*, double2*, double)> matvec;  // w = v - T v, inner tol
+    std::function<double(double)> tau;  // inner tolerance at a relative residual
+    double tau_strict;                  // inner tolerance of the restart residuals
+    std::function<void(int, double)> progress;  // (matvecs so far, relative residual) or empty
+};
+
+int kdots(const Krylov& k, const double2* V, int64_t ld, int nv, const double2* w, cplx* out) {
+    HIPCHK(wdd::blas_multidot(*k.blas, V, ld, nv, w, k.n, k.stream));
+    std::vector<double2> tmp(nv);
+    HIPCHK(hipMemcpyAsync(tmp.data(), k.blas->result, sizeof(double2) * nv, hipMemcpyDeviceToHost,
+                          k.stream));
+    HIPCHK(hipStreamSynchronize(k.stream));
+    for (int i = 0; i < nv; ++i) out[i] = cplx(tmp[i].x, tmp[i].y);
     return DD_OK;
 }
 
-double norm(dd_handle* h, const double2* x) {
+double knorm(const Krylov& k, const double2* x) {
     cplx v;
-    if (dots(h, x, 0, 1, x, &v) != DD_OK) return NAN;
+    if (kdots(k, x, 0, 1, x, &v) != DD_OK) return NAN;
     return std::sqrt(std::max(0.0, v.real()));
 }
 
-int axpby(dd_handle* h, cplx a, const double2* x, cplx b, double2* y) {
+int kaxpby(const Krylov& k, cplx a, const double2* x, cplx b, double2* y) {
     HIPCHK(wdd::blas_axpby(make_double2(a.real(), a.imag()), x, make_double2(b.real(), b.imag()),
-                           y, h->n_if, h->stream));
+                           y, k.n, k.stream));
     return DD_OK;
+}
+
+// The handle's interface-vector operations.
+Krylov handle_vectors(dd_handle* h) {
+    Krylov k{};
+    k.blas = &h->blas;
+    k.stream = h->stream;
+    k.n = h->n_if;
+    k.ld = h->ld;
+    k.m = h->opt.restart;
+    k.V = h->d_V.p;
+    k.r = h->d_r.p;
+    k.coefs = h->d_coefs.p;
+    return k;
+}
+
+int dots(dd_handle* h, const double2* V, int64_t ld, int k, const double2* w, cplx* out) {
+    return kdots(handle_vectors(h), V, ld, k, w, out);
+}
+
+double norm(dd_handle* h, const double2* x) { return knorm(handle_vectors(h), x); }
+
+int axpby(dd_handle* h, cplx a, const double2* x, cplx b, double2* y) {
+    return kaxpby(handle_vectors(h), a, x, b, y);
 }
 
 
@@ -798,19 +837,19 @@ double matvec_tau(const dd_handle* h, double tol, double rel) {
 // sequential ones), complex Givens rotations on the host.  Stops when the
 // recursive residual <= tol * rnorm0 or after max_iter matvecs; returns the
 // iterations and the recursive relative residual.
-int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double tol, int max_iter,
-          int* its_out, double* rel_out) {
-    const int m = h->opt.restart;
-    const int64_t n = h->n_if, ld = h->ld;
-    double2* V = h->d_V.p;
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * n, h->stream));
+int gmres_core(const Krylov& K, const double2* rhs, double2* x, double rnorm0, double tol,
+               int max_iter, int* its_out, double* rel_out) {
+    const int m = K.m;
+    const int64_t n = K.n, ld = K.ld;
+    double2* V = K.V;
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * n, K.stream));
     *its_out = 0;
     *rel_out = rnorm0 == 0.0 ? 0.0 : 1.0;
     if (rnorm0 == 0.0 || max_iter <= 0) return DD_OK;
     std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
     std::vector<double> cs(m);
     std::vector<cplx> h1(m + 1), h2(m + 1);
-    HIPCHK(hipMemcpyAsync(h->d_r.p, rhs, sizeof(double2) * n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(K.r, rhs, sizeof(double2) * n, hipMemcpyDeviceToDevice, K.stream));
     double beta = rnorm0;
     int its = 0;
     double rel = 1.0;
@@ -818,21 +857,21 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
         std::fill(H.begin(), H.end(), cplx(0.0));
         std::fill(g.begin(), g.end(), cplx(0.0));
         g[0] = beta;
-        CHK(axpby(h, cplx(1.0 / beta, 0.0), h->d_r.p, cplx(0.0), V));
+        CHK(kaxpby(K, cplx(1.0 / beta, 0.0), K.r, cplx(0.0), V));
         int k = 0;
         for (int j = 0; j < m; ++j) {
             double2* w = V + (int64_t)(j + 1) * ld;
-            CHK(matvec(h, V + (int64_t)j * ld, w, matvec_tau(h, tol, rel)));
+            CHK(K.matvec(V + (int64_t)j * ld, w, K.tau(rel)));
             ++its;
-            CHK(dots(h, V, ld, j + 1, w, h1.data()));
-            HIPCHK(wdd::blas_multiaxpy(h->blas, V, ld, j + 1, w, n, h->stream));
-            CHK(dots(h, V, ld, j + 1, w, h2.data()));
-            HIPCHK(wdd::blas_multiaxpy(h->blas, V, ld, j + 1, w, n, h->stream));
+            CHK(kdots(K, V, ld, j + 1, w, h1.data()));
+            HIPCHK(wdd::blas_multiaxpy(*K.blas, V, ld, j + 1, w, n, K.stream));
+            CHK(kdots(K, V, ld, j + 1, w, h2.data()));
+            HIPCHK(wdd::blas_multiaxpy(*K.blas, V, ld, j + 1, w, n, K.stream));
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h1[i] + h2[i];
-            const double hn = norm(h, w);
+            const double hn = knorm(K, w);
             if (!std::isfinite(hn)) return fail(DD_ENAN, "non-finite Krylov vector");
             H[(size_t)(j + 1) * m + j] = hn;
-            if (hn > 0.0) CHK(axpby(h, cplx(1.0 / hn, 0.0), w, cplx(0.0), w));
+            if (hn > 0.0) CHK(kaxpby(K, cplx(1.0 / hn, 0.0), w, cplx(0.0), w));
             for (int i = 0; i < j; ++i) {
                 const cplx a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
                 H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
@@ -853,8 +892,7 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
             g[j] = cs[j] * g[j];
             rel = std::abs(g[j + 1]) / rnorm0;
             k = j + 1;
-            if (h->prog && its % h->prog_every == 0)
-                h->prog(h->prog_user, h->prog_base + its, rel * h->prog_scale);
+            if (K.progress) K.progress(its, rel);
             if (!std::isfinite(rel)) return fail(DD_ENAN, "non-finite outer residual");
             if (rel <= tol || its >= max_iter || hn == 0.0) break;
         }
@@ -865,15 +903,15 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
         }
         std::vector<double2> yc(k);
         for (int i = 0; i < k; ++i) yc[i] = make_double2(y[i].real(), y[i].imag());
-        HIPCHK(hipMemcpyAsync(h->d_coefs.p, yc.data(), sizeof(double2) * k, hipMemcpyHostToDevice,
-                              h->stream));
-        HIPCHK(wdd::blas_combine(V, ld, k, h->d_coefs.p, x, n, 1, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipMemcpyAsync(K.coefs, yc.data(), sizeof(double2) * k, hipMemcpyHostToDevice,
+                              K.stream));
+        HIPCHK(wdd::blas_combine(V, ld, k, K.coefs, x, n, 1, K.stream));
+        HIPCHK(hipStreamSynchronize(K.stream));
         if (rel <= tol || its >= max_iter) break;
         // r = rhs - (x - T x), with the strict inner tolerance
-        CHK(matvec(h, x, h->d_r.p, h->opt.tau_in));
-        CHK(axpby(h, cplx(1.0), rhs, cplx(-1.0), h->d_r.p));
-        beta = norm(h, h->d_r.p);
+        CHK(K.matvec(x, K.r, K.tau_strict));
+        CHK(kaxpby(K, cplx(1.0), rhs, cplx(-1.0), K.r));
+        beta = knorm(K, K.r);
         if (!std::isfinite(beta)) return fail(DD_ENAN, "non-finite outer residual");
         rel = beta / rnorm0;
         if (beta == 0.0 || rel <= tol) break;
@@ -881,6 +919,20 @@ int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double to
     *its_out = its;
     *rel_out = rel;
     return DD_OK;
+}
+
+// GMRES of a 2D handle: its sweep operator, inner-tolerance rule and progress callback.
+int gmres(dd_handle* h, const double2* rhs, double2* x, double rnorm0, double tol, int max_iter,
+          int* its_out, double* rel_out) {
+    Krylov K = handle_vectors(h);
+    K.matvec = [h](const double2* v, double2* w, double tau) { return matvec(h, v, w, tau); };
+    K.tau = [h, tol](double rel) { return matvec_tau(h, tol, rel); };
+    K.tau_strict = h->opt.tau_in;
+    if (h->prog)
+        K.progress = [h](int its, double rel) {
+            if (its % h->prog_every == 0) h->prog(h->prog_user, h->prog_base + its, rel * h->prog_scale);
+        };
+    return gmres_core(K, rhs, x, rnorm0, tol, max_iter, its_out, rel_out);
 }
 
 // Plain fixed-point iteration G <- T G + h.  With warm start the sweep
@@ -2616,6 +2668,13 @@ struct dd3_handle {
     DBuf<double2> d_gin, d_gout, d_u;
     DBuf<int> d_iters, d_perm;
     bool has_f = false;
+    // outer solve (allocated by the first dd3_solve)
+    wdd::Blas blas{};
+    int64_t ld = 0;
+    DBuf<double2> d_V, d_r, d_coefs, d_h, d_G, d_tmp, d_ug, d_Su, d_work;
+    int64_t sweeps = 0, wh_total = 0;
+    int wh_max = 0;
+    double dof_updates = 0.0;
 };
 
 namespace {
@@ -2632,6 +2691,10 @@ void dd3_free(dd3_handle* h) {
     h->d_u.free();
     h->d_iters.free();
     h->d_perm.free();
+    for (DBuf<double2>* b : {&h->d_V, &h->d_r, &h->d_coefs, &h->d_h, &h->d_G, &h->d_tmp, &h->d_ug,
+                             &h->d_Su, &h->d_work})
+        b->free();
+    wdd::blas_free(h->blas);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -2701,6 +2764,7 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
     if (o.nt_override < 0 || o.nt_override == 1 || o.nt_override == 2)
         return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
     if (!std::isfinite(o.tau_in)) return fail(DD_EINVAL, "tau_in must be finite");
+    if (o.restart < 1 || o.restart > 400) return fail(DD_EINVAL, "restart must be in [1, 400]");
     const int P = degree;
     const int64_t Nx = (int64_t)box->nx * P + 1, Ny = (int64_t)box->ny * P + 1,
                   Nz = (int64_t)box->nz * P + 1;
@@ -2927,8 +2991,8 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
 }
 
 template <typename Real>
-wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, double src, bool with_f, double tau,
-                                  int max_wh) {
+wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, const double2* gi, double2* go, double src,
+                                  bool with_f, double tau, int max_wh) {
     wdd::Sweep3Args<Real> a{};
     const int64_t nn = h->L * h->nloc;
     const Real* coef = reinterpret_cast<const Real*>(h->d_coef.p);
@@ -2960,8 +3024,8 @@ wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, double src, bool with_f, 
     a.kaph = tab + h->tab_len;
     a.cs = tab + 2 * h->tab_len;
     a.sn = tab + 3 * h->tab_len;
-    a.g_in = h->d_gin.p;
-    a.g_out = h->d_gout.p;
+    a.g_in = gi;
+    a.g_out = go;
     a.src = src;
     a.u = h->d_u.p;
     a.wh_iters = h->d_iters.p;
@@ -2973,21 +3037,84 @@ wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, double src, bool with_f, 
     return a;
 }
 
-// One launch over all box subdomains; optionally timed with events.
-int run_sweep3(dd3_handle* h, double src, bool with_f, double tau, int max_wh, float* ms) {
+// One launch over all box subdomains (g_in -> g_out); optionally timed with
+// events.  Accumulates the WaveHoltz counts of the launch.
+int run_sweep3_io(dd3_handle* h, const double2* gi, double2* go, double src, bool with_f,
+                  double tau, int max_wh, float* ms) {
     const int wg = (int)(((h->nloc + 63) / 64) * 64);
     if (ms) HIPCHK(hipEventRecord(h->ev0, h->stream));
     hipError_t e;
     if (h->opt.precision == DD_FP32)
-        e = wdd::launch_sweep3<float>(sweep3_args<float>(h, src, with_f, tau, max_wh), wg, h->stream);
+        e = wdd::launch_sweep3<float>(sweep3_args<float>(h, gi, go, src, with_f, tau, max_wh), wg,
+                                      h->stream);
     else
-        e = wdd::launch_sweep3<double>(sweep3_args<double>(h, src, with_f, tau, max_wh), wg,
+        e = wdd::launch_sweep3<double>(sweep3_args<double>(h, gi, go, src, with_f, tau, max_wh), wg,
                                        h->stream);
     HIPCHK(e);
     if (ms) HIPCHK(hipEventRecord(h->ev1, h->stream));
+    std::vector<int> its(h->L);
+    HIPCHK(hipMemcpyAsync(its.data(), h->d_iters.p, sizeof(int) * h->L, hipMemcpyDeviceToHost,
+                          h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     if (ms) HIPCHK(hipEventElapsedTime(ms, h->ev0, h->ev1));
+    h->sweeps += 1;
+    for (int64_t l = 0; l < h->L; ++l) {
+        h->wh_total += its[l];
+        h->wh_max = std::max(h->wh_max, its[l]);
+        h->dof_updates += (double)h->nloc * (h->nt[l] - 1) * its[l];
+        if (its[l] < 1) return fail(DD_EHIP, "box sweep reported no WaveHoltz iteration");
+    }
     return DD_OK;
+}
+
+int run_sweep3(dd3_handle* h, double src, bool with_f, double tau, int max_wh, float* ms) {
+    return run_sweep3_io(h, h->d_gin.p, h->d_gout.p, src, with_f, tau, max_wh, ms);
+}
+
+int ensure_solver3(dd3_handle* h) {
+    if (h->d_V.p) return DD_OK;
+    const int m = h->opt.restart;
+    h->ld = ((h->n_if + 63) / 64) * 64;
+    HIPCHK(h->d_V.alloc((size_t)(m + 1) * h->ld));
+    HIPCHK(h->d_r.alloc(h->n_if));
+    HIPCHK(h->d_coefs.alloc(m + 1));
+    HIPCHK(h->d_h.alloc(h->n_if));
+    HIPCHK(h->d_G.alloc(h->n_if));
+    HIPCHK(h->d_tmp.alloc(h->n_if));
+    HIPCHK(h->d_ug.alloc(h->N));
+    HIPCHK(h->d_Su.alloc(h->N));
+    HIPCHK(h->d_work.alloc(h->N));
+    HIPCHK(wdd::blas_init(h->blas, m + 2, h->stream));
+    return DD_OK;
+}
+
+wdd::Operator3Args op3_args(const dd3_handle* h) {
+    wdd::Operator3Args a{};
+    a.Nx = h->Nx;
+    a.Ny = h->Ny;
+    a.Nz = h->Nz;
+    a.P = h->P;
+    a.nx = h->box.nx;
+    a.ny = h->box.ny;
+    a.nz = h->box.nz;
+    // z chunks: enough workgroups to fill the chip (about 2048), chunks of
+    // at least 4P planes so the 2P-plane warm-up of the z window stays small
+    const int64_t tiles = (int64_t)((h->Nx + 63) / 64) * ((h->Ny + 3) / 4);
+    const int64_t nkc = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles,
+                                                               h->Nz / (4 * h->P)));
+    a.kchunk = (int)((h->Nz + nkc - 1) / nkc);
+    a.sx_ref = 2.0 / h->hx;
+    a.sy_ref = 2.0 / h->hy;
+    a.sz_ref = 2.0 / h->hz;
+    a.wx = h->d_wx.p;
+    a.wy = h->d_wy.p;
+    a.wz = h->d_wz.p;
+    a.M = h->d_M.p;
+    a.H = h->d_H.p;
+    a.omega = h->omega;
+    for (int i = 0; i <= h->P; ++i)
+        for (int j = 0; j <= h->P; ++j) a.K1[i][j] = h->K1[i][j];
+    return a;
 }
 
 }  // namespace
@@ -3135,33 +3262,122 @@ int dd3_apply_operator_device(dd3_handle* h, void* stream, const double* d_x, do
     CHK(validate3(h));
     if (!d_x || !d_y) return fail(DD_EINVAL, "null array");
     HIPCHK(hipSetDevice(h->dev));
-    wdd::Operator3Args a{};
-    a.Nx = h->Nx;
-    a.Ny = h->Ny;
-    a.Nz = h->Nz;
-    a.P = h->P;
-    a.nx = h->box.nx;
-    a.ny = h->box.ny;
-    a.nz = h->box.nz;
-    // z chunks: enough workgroups to fill the chip (about 2048), chunks of
-    // at least 4P planes so the 2P-plane warm-up of the z window stays small
-    const int64_t tiles = (int64_t)((h->Nx + 63) / 64) * ((h->Ny + 3) / 4);
-    const int64_t nkc = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles,
-                                                               h->Nz / (4 * h->P)));
-    a.kchunk = (int)((h->Nz + nkc - 1) / nkc);
-    a.sx_ref = 2.0 / h->hx;
-    a.sy_ref = 2.0 / h->hy;
-    a.sz_ref = 2.0 / h->hz;
-    a.wx = h->d_wx.p;
-    a.wy = h->d_wy.p;
-    a.wz = h->d_wz.p;
-    a.M = h->d_M.p;
-    a.H = h->d_H.p;
-    a.omega = h->omega;
-    for (int i = 0; i <= h->P; ++i)
-        for (int j = 0; j <= h->P; ++j) a.K1[i][j] = h->K1[i][j];
     hipStream_t s = stream ? (hipStream_t)stream : h->stream;
-    HIPCHK(wdd::launch_operator3(a, (const double2*)d_x, (double2*)d_y, s));
+    HIPCHK(wdd::launch_operator3(op3_args(h), (const double2*)d_x, (double2*)d_y, s));
+    return DD_OK;
+}
+
+int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol, int max_iter,
+              double* u_re, double* u_im, dd_stats* st) {
+    CHK(validate3(h));
+    if (!u_re || !u_im) return fail(DD_EINVAL, "null output");
+    if (!(tol > 0.0) || max_iter < 1) return fail(DD_EINVAL, "tol must be > 0, max_iter >= 1");
+    if (!f_re && f_im) return fail(DD_EINVAL, "f_im given without f_re");
+    CHK(check_finite(f_re, h->N, "f_re"));
+    CHK(check_finite(f_im, h->N, "f_im"));
+    HIPCHK(hipSetDevice(h->dev));
+    const auto t0 = std::chrono::steady_clock::now();
+    CHK(ensure_solver3(h));
+    const bool with_f = f_re != nullptr;
+    if (with_f) {
+        HIPCHK(hipMemcpy(h->d_f.p, f_re, 8 * h->N, hipMemcpyHostToDevice));
+        if (f_im)
+            HIPCHK(hipMemcpy(h->d_f.p + h->N, f_im, 8 * h->N, hipMemcpyHostToDevice));
+        else
+            HIPCHK(hipMemset(h->d_f.p + h->N, 0, 8 * h->N));
+    }
+    h->sweeps = h->wh_total = 0;
+    h->wh_max = 0;
+    h->dof_updates = 0.0;
+    const double tau = std::max(h->opt.tau_in, 0.0);
+    const int mwh = h->opt.max_wh;
+    // h = sweep(0, sources on): the affine part of the sweep map (no outer
+    // boundary data in the box problem)
+    HIPCHK(hipMemsetAsync(h->d_tmp.p, 0, sizeof(double2) * h->n_if, h->stream));
+    CHK(run_sweep3_io(h, h->d_tmp.p, h->d_h.p, 1.0, with_f, tau, mwh, nullptr));
+    Krylov K{};
+    K.blas = &h->blas;
+    K.stream = h->stream;
+    K.n = h->n_if;
+    K.ld = h->ld;
+    K.m = h->opt.restart;
+    K.V = h->d_V.p;
+    K.r = h->d_r.p;
+    K.coefs = h->d_coefs.p;
+    K.matvec = [h, mwh](const double2* v, double2* w, double t) {
+        CHK(run_sweep3_io(h, v, w, 0.0, false, t, mwh, nullptr));
+        return kaxpby(Krylov{&h->blas, h->stream, h->n_if}, cplx(1.0), v, cplx(-1.0), w);
+    };
+    K.tau = [tau](double) { return tau; };
+    K.tau_strict = tau;
+    const double hn = knorm(K, h->d_h.p);
+    if (!std::isfinite(hn)) return fail(DD_ENAN, "non-finite interface data");
+    int its = 0;
+    double rel = 0.0;
+    CHK(gmres_core(K, h->d_h.p, h->d_G.p, hn, tol, max_iter, &its, &rel));
+    // u from the final sweep of G with sources on (g_fin = T G + h), glued
+    // to the global nodes; true interface residual ||g_fin - G|| / ||h||
+    CHK(run_sweep3_io(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, tau, mwh, nullptr));
+    CHK(kaxpby(K, cplx(-1.0), h->d_G.p, cplx(1.0), h->d_tmp.p));
+    const double rtrue = hn > 0.0 ? knorm(K, h->d_tmp.p) / hn : 0.0;
+    HIPCHK(wdd::launch_glue3(op3_args(h), h->d_u.p, h->mx, h->my, h->mz, h->part.sx, h->part.sy,
+                             h->part.sz, h->d_ug.p, h->stream));
+    std::vector<double2> u(h->N);
+    HIPCHK(hipMemcpyAsync(u.data(), h->d_ug.p, sizeof(double2) * h->N, hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < h->N; ++i) {
+        u_re[i] = u[i].x;
+        u_im[i] = u[i].y;
+    }
+    rel = std::max(rel, rtrue);
+    if (!std::isfinite(rel)) return fail(DD_ENAN, "non-finite outer residual");
+    if (st) {
+        *st = dd_stats{};
+        st->outer_iters = its;
+        st->sweeps = (int)h->sweeps;
+        st->rel_residual = rel;
+        st->true_rel_residual = rtrue;
+        st->wh_iters_total = h->wh_total;
+        st->wh_iters_max = h->wh_max;
+        st->nt_min = *std::min_element(h->nt.begin(), h->nt.end());
+        st->nt_max = h->nt_max;
+        st->dof_updates = h->dof_updates;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rel <= tol ? DD_OK : DD_ENOTCONV;
+}
+
+int dd3_residual(dd3_handle* h, const double* u_re, const double* u_im, const double* f_re,
+                 const double* f_im, double* rel) {
+    CHK(validate3(h));
+    if (!u_re || !u_im || !rel) return fail(DD_EINVAL, "null argument");
+    if (!f_re && f_im) return fail(DD_EINVAL, "f_im given without f_re");
+    CHK(check_finite(u_re, h->N, "u_re"));
+    CHK(check_finite(u_im, h->N, "u_im"));
+    CHK(check_finite(f_re, h->N, "f_re"));
+    CHK(check_finite(f_im, h->N, "f_im"));
+    HIPCHK(hipSetDevice(h->dev));
+    CHK(ensure_solver3(h));
+    std::vector<double2> u(h->N);
+    for (int64_t i = 0; i < h->N; ++i) u[i] = make_double2(u_re[i], u_im[i]);
+    HIPCHK(hipMemcpy(h->d_ug.p, u.data(), sizeof(double2) * h->N, hipMemcpyHostToDevice));
+    if (f_re) {
+        HIPCHK(hipMemcpy(h->d_f.p, f_re, 8 * h->N, hipMemcpyHostToDevice));
+        if (f_im)
+            HIPCHK(hipMemcpy(h->d_f.p + h->N, f_im, 8 * h->N, hipMemcpyHostToDevice));
+        else
+            HIPCHK(hipMemset(h->d_f.p + h->N, 0, 8 * h->N));
+    }
+    HIPCHK(wdd::launch_operator3(op3_args(h), h->d_ug.p, h->d_Su.p, h->stream));
+    HIPCHK(wdd::launch_residual3(op3_args(h), f_re ? h->d_f.p : nullptr,
+                                 f_re ? h->d_f.p + h->N : nullptr, h->d_Su.p, h->d_work.p,
+                                 h->stream));
+    HIPCHK(wdd::blas_sum2(h->blas, h->d_work.p, h->N, h->stream));
+    double2 sums;
+    HIPCHK(hipMemcpyAsync(&sums, h->blas.result, sizeof(double2), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    *rel = sums.y > 0.0 ? std::sqrt(sums.x / sums.y) : std::sqrt(sums.x);
     return DD_OK;
 }
 

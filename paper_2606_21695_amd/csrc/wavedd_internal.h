@@ -222,5 +222,11 @@ struct Operator3Args {
     double K1[kMaxP + 1][kMaxP + 1];
 };
 hipError_t launch_operator3(const Operator3Args& a, const double2* x, double2* y, hipStream_t s);
+// ug = mean of the subdomain copies of every global node.
+hipError_t launch_glue3(const Operator3Args& a, const double2* usub, int mx, int my, int mz, int sx,
+                        int sy, int sz, double2* ug, hipStream_t s);
+// work[g] = (|b - Su|^2, |b|^2), b = (f, phi) at the global nodes (f may be null).
+hipError_t launch_residual3(const Operator3Args& a, const double* f_re, const double* f_im,
+                            const double2* Su, double2* work, hipStream_t s);
 
 }  // namespace wdd

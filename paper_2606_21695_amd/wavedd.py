@@ -32,7 +32,7 @@ EXPORTS = [
     "dd_engine_create", "dd_engine_destroy", "dd_engine_submit", "dd_engine_status",
     "dd_engine_wait", "dd_engine_get_info", "dd_engine_wait_any", "dd_set_progress",
     "dd3_setup", "dd3_destroy", "dd3_sizes", "dd3_time_steps", "dd3_mesh_coords", "dd3_sweep",
-    "dd3_time_sweep", "dd3_apply_operator_device",
+    "dd3_time_sweep", "dd3_apply_operator_device", "dd3_solve", "dd3_residual",
 ]
 DD_REQ_QUEUED, DD_REQ_RUNNING, DD_REQ_DONE = 0, 1, 2
 
@@ -187,6 +187,8 @@ def load():
         "dd3_sweep": ([P, D, D, D, D, C.c_double, D, D, D, D, C.POINTER(C.c_int)], C.c_int),
         "dd3_time_sweep": ([P, C.c_int, C.c_int, D, D], C.c_int),
         "dd3_apply_operator_device": ([P, P, P, P], C.c_int),
+        "dd3_solve": ([P, D, D, C.c_double, C.c_int, D, D, C.POINTER(dd_stats)], C.c_int),
+        "dd3_residual": ([P, D, D, D, D, D], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -650,3 +652,33 @@ def dd3_apply_operator_device(h, x, y, stream=None):
     sp = None if stream is None else C.c_void_p(stream.cuda_stream)
     _check(load().dd3_apply_operator_device(h, sp, C.c_void_p(x.data_ptr()),
                                             C.c_void_p(y.data_ptr())))
+
+
+def dd3_solve(h, f=None, tol=1e-8, max_iter=1000, allow_notconv=False):
+    """Box solve from host arrays; f at the global nodes (real or complex).
+    Returns (u complex N-array, stats dict, return code)."""
+    n = dd3_sizes(h)["n_global"]
+    f_re = f_im = None
+    if f is not None:
+        f = np.asarray(f)
+        f_re = _f64(f.real)
+        f_im = _f64(f.imag) if np.iscomplexobj(f) else None
+    u_re, u_im = np.empty(n), np.empty(n)
+    st = dd_stats()
+    rc = load().dd3_solve(h, _dp(f_re), _dp(f_im), tol, max_iter, _dp(u_re), _dp(u_im),
+                          C.byref(st))
+    _check(rc, (DD_ENOTCONV,) if allow_notconv else ())
+    return u_re + 1j * u_im, st.as_dict(), rc
+
+
+def dd3_residual(h, u, f=None):
+    u = np.asarray(u, dtype=complex)
+    f_re = f_im = None
+    if f is not None:
+        f = np.asarray(f)
+        f_re = _f64(f.real)
+        f_im = _f64(f.imag) if np.iscomplexobj(f) else None
+    rel = C.c_double()
+    _check(load().dd3_residual(h, _dp(_f64(u.real)), _dp(_f64(u.imag)), _dp(f_re), _dp(f_im),
+                               C.byref(rel)))
+    return rel.value

@@ -258,3 +258,75 @@ def test_c6_full_size_sweep_sampled(gpu_lib, prec):
             want = (-gl[one.face_off[face]:one.face_off[face] + one.face_len[face]]
                     - 2j * (wl.omega / one.subs[0]["c"][nodes]) * u_ref[nodes])
             assert _rel([sent], [want]) < tol, (l, face)
+
+
+def test_solve_matches_oracle_dd(gpu_lib):
+    """Outer FP64 GMRES over box sweeps (WaveHoltz to 1e-12) against the
+    oracle's DD with exact subdomain solves at the same outer tolerance."""
+    from oracle import dd
+    W = gpu_lib
+    shape, om, tol = (4, 4, 4, 2, 2, 2, 2), 6.0, 1e-8
+    h, Xl, Yl, Zl = _setup(W, shape, om, tau_in=1e-12, max_wh=400)
+    dec, X, Y, Z = _oracle(shape, om)
+    u, st, _ = W.dd3_solve(h, _src(Xl, Yl, Zl), tol)
+    rel_res = W.dd3_residual(h, u, _src(Xl, Yl, Zl))
+    W.dd3_destroy(h)
+    us_ref, info = dd.solve_dd(dec, _src(X, Y, Z), tol=tol)
+    print(f"box solve gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
+    assert abs(st["outer_iters"] - info["iters"]) <= 1
+    assert _rel([u], [dec.glue(us_ref)]) < 1e-9
+    assert st["true_rel_residual"] < 2 * tol
+    S, _, _, _ = sem3.system(dec.mesh, _c3(X, Y, Z), om)
+    b = sem3.load(dec.mesh, _src(X, Y, Z))
+    assert rel_res == pytest.approx(np.linalg.norm(b - S @ u) / np.linalg.norm(b), rel=1e-9)
+
+
+def test_solve_tight_matches_global_lu(gpu_lib):
+    W = gpu_lib
+    shape, om = (3, 2, 4, 3, 3, 1, 2), 6.0
+    h, Xl, Yl, Zl = _setup(W, shape, om, tau_in=1e-14, max_wh=1000)
+    mesh = sem3.Box(*shape[:4], *BOX)
+    X, Y, Z = sem3.node_coords(mesh)
+    u, st, _ = W.dd3_solve(h, _src(Xl, Yl, Zl) * (1 + 0.5j), 1e-12)
+    rel_res = W.dd3_residual(h, u, _src(Xl, Yl, Zl) * (1 + 0.5j))
+    W.dd3_destroy(h)
+    u_lu = sem3.solve(mesh, _c3(X, Y, Z), om, _src(X, Y, Z) * (1 + 0.5j))
+    assert _rel([u], [u_lu]) < 1e-10
+    assert rel_res < 1e-10
+
+
+def test_solve_fp32_sweeps(gpu_lib):
+    """FP32 box sweeps under the FP64 outer GMRES reach the answer to the
+    FP32 sweep accuracy (no refinement in the box solve)."""
+    W = gpu_lib
+    shape, om = (4, 4, 4, 2, 2, 2, 2), 6.0
+    h, Xl, Yl, Zl = _setup(W, shape, om, precision=1, tau_in=1e-6, max_wh=400)
+    mesh = sem3.Box(*shape[:4], *BOX)
+    X, Y, Z = sem3.node_coords(mesh)
+    u, st, rc = W.dd3_solve(h, _src(Xl, Yl, Zl), 1e-5, allow_notconv=True)
+    W.dd3_destroy(h)
+    u_lu = sem3.solve(mesh, _c3(X, Y, Z), om, _src(X, Y, Z))
+    print(f"box fp32 rc={rc} iters={st['outer_iters']} err={_rel([u], [u_lu]):.2e}", flush=True)
+    assert _rel([u], [u_lu]) < 1e-4
+
+
+def test_c6_small_solve_matches_oracle_dd(gpu_lib):
+    """The c6 subdomain shape at 8^3 elements: GPU machine solve against the
+    oracle DD (exact subdomain solves)."""
+    import workloads
+    from oracle import dd
+    W = gpu_lib
+    wl = workloads.c6_small()
+    X, Y, Z = W.dd3_mesh_coords(wl.nx, wl.ny, wl.nz, wl.P, *wl.box)
+    o = W.dd_default_options(tau_in=1e-12, max_wh=400)
+    h = W.dd3_setup(wl.nx, wl.ny, wl.nz, wl.P, wl.c(X, Y, Z), wl.omega, wl.sx, wl.sy, wl.sz,
+                    *wl.box, options=o)
+    u, st, _ = W.dd3_solve(h, wl.f(X, Y, Z), 1e-8)
+    W.dd3_destroy(h)
+    mesh = sem3.Box(wl.nx, wl.ny, wl.nz, wl.P, *wl.box)
+    Xo, Yo, Zo = sem3.node_coords(mesh)
+    dec = dd3.Decomposition3(mesh, dd3.Partition3(wl.sx, wl.sy, wl.sz), wl.c(Xo, Yo, Zo), wl.omega)
+    us_ref, info = dd.solve_dd(dec, wl.f(Xo, Yo, Zo), tol=1e-8)
+    print(f"c6_small solve gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
+    assert abs(st["outer_iters"] - info["iters"]) <= 1
+    assert _rel([u], [dec.glue(us_ref)]) < 1e-9
