@@ -42,8 +42,8 @@ MEASURED_TRAFFIC = {
 # HBM bytes per launch of the box (3D) sweep kernel, same counters and scale,
 # keyed by the hash of the box kernel source (comments ignored).
 MEASURED_TRAFFIC3 = {
-    ("d62ef9d7610971a1", "c6", "fp64"): round((418575.0 * 2.0 + 331907.2) * 1024),
-    ("d62ef9d7610971a1", "c6", "fp32"): round((332785.8 * 2.0 + 333685.0) * 1024),
+    ("b5d79508330583c9", "c6", "fp64"): round((754258.0 * 2.0 + 1754764.2) * 1024),
+    ("b5d79508330583c9", "c6", "fp32"): round((332686.2 * 2.0 + 333535.6) * 1024),
 }
 
 # section markers of each layout in the kernel source

@@ -234,7 +234,7 @@ __device__ void sweep3_item(const Sweep3Args<Real>& A, const Sub3& d, int item, 
 }
 
 template <typename Real, int P>
-__global__ void __launch_bounds__(kMaxWG) sweep3_kernel(const Sweep3Args<Real> A) {
+__device__ __forceinline__ void sweep3_items(const Sweep3Args<Real>& A) {
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
@@ -243,6 +243,20 @@ __global__ void __launch_bounds__(kMaxWG) sweep3_kernel(const Sweep3Args<Real> A
         sweep3_item<Real, P>(A, d, item, lds, red);
         __syncthreads();
     }
+}
+
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) sweep3_kernel(const Sweep3Args<Real> A) {
+    sweep3_items<Real, P>(A);
+}
+
+// The same kernel built to allow 6 waves per SIMD (at most 80 VGPRs): 3-4
+// small-subdomain workgroups then share a CU.  Only the prologue spills;
+// the step loop does not.
+template <typename Real, int P>
+__global__ void __launch_bounds__(kMaxWG) __attribute__((amdgpu_waves_per_eu(6, 8)))
+sweep3_kernel_capped(const Sweep3Args<Real> A) {
+    sweep3_items<Real, P>(A);
 }
 
 // y = S x on the whole box.  A workgroup owns a 64 x 4 tile of (x, y)
@@ -403,19 +417,31 @@ void sweep3_thread_order(int nxl, int nyl, int nzl, int P, size_t real_size, int
     }
 }
 
+// The register-capped build pays off for FP64 at P <= 3 when a workgroup is
+// at most 12 waves (measured: 343- and 729-node subdomains 1.3x faster;
+// FP32, P = 4 and 1000-node subdomains were slower with it).
+template <typename Real, int P>
+void launch_sweep3_p(const Sweep3Args<Real>& a, int wg, hipStream_t s) {
+    if constexpr (sizeof(Real) == 8 && P <= 3) {
+        if (wg <= 768) {
+            hipLaunchKernelGGL((sweep3_kernel_capped<Real, P>), dim3(a.n_items), dim3(wg),
+                               a.lds_bytes, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((sweep3_kernel<Real, P>), dim3(a.n_items), dim3(wg), a.lds_bytes, s, a);
+}
+
 template <typename Real>
 hipError_t launch_sweep3(const Sweep3Args<Real>& a, int wg, hipStream_t s) {
     if (wg > kMaxWG) return hipErrorInvalidValue;
-#define L(PP) \
-    hipLaunchKernelGGL((sweep3_kernel<Real, PP>), dim3(a.n_items), dim3(wg), a.lds_bytes, s, a)
     switch (a.P) {
-        case 1: L(1); break;
-        case 2: L(2); break;
-        case 3: L(3); break;
-        case 4: L(4); break;
+        case 1: launch_sweep3_p<Real, 1>(a, wg, s); break;
+        case 2: launch_sweep3_p<Real, 2>(a, wg, s); break;
+        case 3: launch_sweep3_p<Real, 3>(a, wg, s); break;
+        case 4: launch_sweep3_p<Real, 4>(a, wg, s); break;
         default: return hipErrorInvalidValue;
     }
-#undef L
     return hipGetLastError();
 }
 
