@@ -1248,14 +1248,17 @@ __global__ void __launch_bounds__(WG) apply_patch1_kernel(const SweepArgs<Real> 
 // NODE layout (one DOF per thread)
 // ---------------------------------------------------------------------------
 
-// Padded LDS grid: (nxl + 2kMaxP) x (nyl + 2kMaxP) per buffer, two buffers,
-// then the element matrix and the per-step tables.
-__host__ __device__ inline int node_stride(int nxl) { return nxl + 2 * kMaxP; }
-__host__ __device__ inline int node_buf(int nxl, int nyl) {
-    return (nxl + 2 * kMaxP) * (nyl + 2 * kMaxP);
+// Padded LDS grid: rows of nxl + G words (kMaxP zeros on the left, the rest
+// on the right) x (nyl + 2kMaxP) rows per buffer, two buffers, then the
+// element matrix and the per-step tables.  G = 256 B / word size: a row
+// stride equal to nxl modulo G gives consecutive lanes (consecutive nodes,
+// across row ends too) consecutive LDS banks in every stencil tap.
+__host__ __device__ inline int node_stride(int nxl, int rs) { return nxl + 256 / rs; }
+__host__ __device__ inline int node_buf(int nxl, int nyl, int rs) {
+    return node_stride(nxl, rs) * (nyl + 2 * kMaxP);
 }
-__host__ __device__ inline int node_tab_off(int nxl, int nyl) {
-    return (2 * node_buf(nxl, nyl) + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
+__host__ __device__ inline int node_tab_off(int nxl, int nyl, int rs) {
+    return (2 * node_buf(nxl, nyl, rs) + (kMaxP + 1) * (kMaxP + 1) + 3) & ~3;
 }
 
 template <typename Real, int P>
@@ -1267,18 +1270,18 @@ struct NodeCtx {
 
     __device__ void setup(const SubDesc& d, Real* lds, const double (*K1)[kMaxP + 1]) {
         const int nxl = d.nxl, nyl = d.nyl, tid = threadIdx.x;
-        const int nb = node_buf(nxl, nyl);
+        const int nb = node_buf(nxl, nyl, (int)sizeof(Real));
         buf0 = lds;
         buf1 = lds + nb;
         Real* kl = lds + 2 * nb;
-        TAB = lds + node_tab_off(nxl, nyl);
+        TAB = lds + node_tab_off(nxl, nyl, (int)sizeof(Real));
         for (int i = tid; i < 2 * nb; i += blockDim.x) lds[i] = Real(0);
         if (tid < (P + 1) * (P + 1)) kl[tid] = (Real)K1[tid / (P + 1)][tid % (P + 1)];
         __syncthreads();
         has = tid < nxl * nyl;
         il = has ? tid % nxl : 0;
         jl = has ? tid / nxl : 0;
-        stride = node_stride(nxl);
+        stride = node_stride(nxl, (int)sizeof(Real));
         pidx = (jl + kMaxP) * stride + il + kMaxP;
         window_coeffs<Real, P>(wxk, il, d.mx, kl);
         window_coeffs<Real, P>(wyk, jl, d.my, kl);
@@ -1302,7 +1305,7 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
                                 double* red) {
     NodeCtx<Real, P> C;
     C.setup(d, lds, A.K1[P]);
-    stage_tables(A, d, lds + node_tab_off(d.nxl, d.nyl));
+    stage_tables(A, d, lds + node_tab_off(d.nxl, d.nyl, (int)sizeof(Real)));
     Slot<Real> s;
     slot_zero(s);
     if (C.has) slot_load(s, A, d, C.il, C.jl);
@@ -1724,7 +1727,8 @@ size_t patch1_lds_bytes(int mx, int my, int P, int wg, int nt_max, size_t real_s
 }
 
 size_t node_lds_bytes(int nxl, int nyl, int nt_max, size_t real_size) {
-    return 40 * sizeof(double) + ((size_t)node_tab_off(nxl, nyl) + 4 * (size_t)nt_max) * real_size;
+    return 40 * sizeof(double) +
+           ((size_t)node_tab_off(nxl, nyl, (int)real_size) + 4 * (size_t)nt_max) * real_size;
 }
 
 #define WDD_DISPATCH_P(P, CALL) \
