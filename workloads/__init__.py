@@ -33,6 +33,7 @@ Box (3D) workloads, the paper's second benchmark family (constant c on
 * ``c6_p1``  128^3 elements, P=1, 16^3 subdomains of 8^3 elements (729 nodes).
 * ``c6_small`` 8^3 elements, P=3, 4^3 subdomains of 2^3 elements: the ``c6``
              subdomain shape at a size the oracle finishes in seconds.
+* ``c6_tiny`` 4^3 elements, P=2, 2^3 subdomains (the smoke check).
 """
 from dataclasses import dataclass, field
 from typing import Callable, Optional
@@ -285,4 +286,10 @@ def c6_small():
     return _box("c6_small", 8, 3, 2)
 
 
-CONFIGS3 = {"c6": c6, "c6_p1": c6_p1, "c6_small": c6_small}
+def c6_tiny():
+    """4^3 elements, P=2, 2^3 subdomains of 2^3 elements: a box problem whose
+    global LU takes milliseconds."""
+    return _box("c6_tiny", 4, 2, 2)
+
+
+CONFIGS3 = {"c6": c6, "c6_p1": c6_p1, "c6_small": c6_small, "c6_tiny": c6_tiny}
