@@ -330,3 +330,23 @@ def test_c6_small_solve_matches_oracle_dd(gpu_lib):
     print(f"c6_small solve gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
     assert abs(st["outer_iters"] - info["iters"]) <= 1
     assert _rel([u], [dec.glue(us_ref)]) < 1e-9
+
+
+def test_solve_zero_source_and_bad_arguments(gpu_lib):
+    """No source: u = 0 without outer iterations; bad tolerances, iteration
+    counts and non-finite sources are rejected before any device work."""
+    W = gpu_lib
+    h, _, _, _ = _setup(W, (4, 4, 4, 2, 2, 2, 2), 6.0)
+    u, st, rc = W.dd3_solve(h, None, 1e-8)
+    assert rc == 0 and st["outer_iters"] == 0 and np.all(u == 0)
+    for tol, it in ((0.0, 10), (1e-8, 0)):
+        with pytest.raises(W.WaveddError) as ei:
+            W.dd3_solve(h, None, tol, it)
+        assert ei.value.code == W.DD_EINVAL
+    n = W.dd3_sizes(h)["n_global"]
+    f = np.ones(n)
+    f[3] = np.nan
+    with pytest.raises(W.WaveddError) as ei:
+        W.dd3_solve(h, f, 1e-8)
+    assert ei.value.code == W.DD_ENAN
+    W.dd3_destroy(h)
