@@ -273,7 +273,7 @@ def test_solve_matches_oracle_dd(gpu_lib):
     W.dd3_destroy(h)
     us_ref, info = dd.solve_dd(dec, _src(X, Y, Z), tol=tol)
     print(f"box solve gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
-    assert abs(st["outer_iters"] - info["iters"]) <= 1
+    assert st["outer_iters"] == info["iters"]
     assert _rel([u], [dec.glue(us_ref)]) < 1e-9
     assert st["true_rel_residual"] < 2 * tol
     S, _, _, _ = sem3.system(dec.mesh, _c3(X, Y, Z), om)
@@ -328,7 +328,7 @@ def test_c6_small_solve_matches_oracle_dd(gpu_lib):
     dec = dd3.Decomposition3(mesh, dd3.Partition3(wl.sx, wl.sy, wl.sz), wl.c(Xo, Yo, Zo), wl.omega)
     us_ref, info = dd.solve_dd(dec, wl.f(Xo, Yo, Zo), tol=1e-8)
     print(f"c6_small solve gpu iters={st['outer_iters']} oracle iters={info['iters']}", flush=True)
-    assert abs(st["outer_iters"] - info["iters"]) <= 1
+    assert st["outer_iters"] == info["iters"]
     assert _rel([u], [dec.glue(us_ref)]) < 1e-9
 
 
