@@ -311,7 +311,7 @@ def test_solve_fp32_sweeps(gpu_lib):
 
 
 def test_c6_small_solve_matches_oracle_dd(gpu_lib):
-    """The c6 subdomain shape at 8^3 elements: GPU machine solve against the
+    """The c6 subdomain shape at 8^3 elements: box solve on the GPU against the
     oracle DD (exact subdomain solves)."""
     import workloads
     from oracle import dd
