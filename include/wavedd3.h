@@ -30,10 +30,10 @@
  *   writes 0 there.
  *
  * Options: dd_options from wavedd.h; precision, tau_in, max_wh, cfl,
- * nt_override and restart are used (tau_in <= 0 runs exactly max_wh
- * WaveHoltz iterations); the outer method is always GMRES without
- * refinement, and the layout, refine, relax, warm-start and tc2 fields are
- * ignored.  Errors, threading and memory ownership as in wavedd.h.
+ * nt_override, restart and refine are used (tau_in <= 0 runs exactly max_wh
+ * WaveHoltz iterations); the outer method is always GMRES, and the layout,
+ * relax, warm-start and tc2 fields are ignored.  Errors, threading and
+ * memory ownership as in wavedd.h.
  */
 #ifndef WAVEDD3_H
 #define WAVEDD3_H
@@ -98,13 +98,19 @@ int dd3_time_sweep(dd3_handle* h, int reps, int fixed_iters, double* ms, double*
  * NULL; no outer boundary data): restarted GMRES (dd_options.restart) in
  * FP64 on (I - T) G = h over box sweeps (Sec. III last paragraph), T the
  * sweep with sources off, h = sweep(0) with sources on, every sweep's
- * WaveHoltz solves to tau_in (cap max_wh) in the handle's precision; then
- * u from the sweep of the converged G, glued at the global nodes (mean of
- * the subdomain copies).  u_re, u_im: N host values.  st (may be NULL):
- * outer iterations, sweeps, rel_residual = max(GMRES estimate, true
- * residual), true_rel_residual = ||h - (I - T) G|| / ||h|| from the final
- * sweep, WaveHoltz totals, DOF-updates, seconds.  Returns DD_ENOTCONV
- * (outputs written) when max_iter is reached first. */
+ * WaveHoltz solves to tau_in (cap max_wh) in the handle's precision.  FP32
+ * handles with refine > 0 (Sec. VII-A: the DD as a lower-precision
+ * operator) run FP64 iterative refinement: h, the residuals
+ * r = h - (I - T) G and u come from FP64 sweeps (WaveHoltz tolerance
+ * clamp(0.01 tol, 1e-13, 1e-8)), the corrections G += GMRES((I - T) d = r)
+ * from FP32 sweeps, at most `refine` extra corrections.  u is the sweep of
+ * the converged G, glued at the global nodes (mean of the subdomain
+ * copies).  u_re, u_im: N host values.  st (may be NULL): outer
+ * iterations, sweeps, refine_steps, rel_residual = max(GMRES estimate,
+ * true residual), true_rel_residual = ||h - (I - T) G|| / ||h|| from the
+ * final sweep, WaveHoltz totals, DOF-updates, seconds.  Returns
+ * DD_ENOTCONV (outputs written) when max_iter or the corrections run out
+ * first. */
 int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol, int max_iter,
               double* u_re, double* u_im, dd_stats* st);
 

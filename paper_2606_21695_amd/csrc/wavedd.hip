@@ -2664,6 +2664,7 @@ struct dd3_handle {
     DBuf<wdd::Sub3> d_desc;
     DBuf<unsigned char> d_coef;  // alpha, betaX, betaY, betaZ, beta (Real, nn each)
     DBuf<unsigned char> d_tab;   // kap, kaph, cs, sn (Real, tab_len each)
+    DBuf<unsigned char> d_coef64, d_tab64;  // FP64 copies of an FP32 handle (refinement sweeps)
     DBuf<double> d_w1d, d_kside, d_wx, d_wy, d_wz, d_M, d_H, d_f;
     DBuf<double2> d_gin, d_gout, d_u;
     DBuf<int> d_iters, d_perm;
@@ -2671,7 +2672,7 @@ struct dd3_handle {
     // outer solve (allocated by the first dd3_solve)
     wdd::Blas blas{};
     int64_t ld = 0;
-    DBuf<double2> d_V, d_r, d_coefs, d_h, d_G, d_tmp, d_ug, d_Su, d_work;
+    DBuf<double2> d_V, d_r, d_coefs, d_h, d_G, d_tmp, d_ug, d_Su, d_work, d_res, d_D;
     int64_t sweeps = 0, wh_total = 0;
     int wh_max = 0;
     double dof_updates = 0.0;
@@ -2683,6 +2684,8 @@ void dd3_free(dd3_handle* h) {
     h->d_desc.free();
     h->d_coef.free();
     h->d_tab.free();
+    h->d_coef64.free();
+    h->d_tab64.free();
     for (DBuf<double>* b : {&h->d_w1d, &h->d_kside, &h->d_wx, &h->d_wy, &h->d_wz, &h->d_M, &h->d_H,
                             &h->d_f})
         b->free();
@@ -2692,7 +2695,7 @@ void dd3_free(dd3_handle* h) {
     h->d_iters.free();
     h->d_perm.free();
     for (DBuf<double2>* b : {&h->d_V, &h->d_r, &h->d_coefs, &h->d_h, &h->d_G, &h->d_tmp, &h->d_ug,
-                             &h->d_Su, &h->d_work})
+                             &h->d_Su, &h->d_work, &h->d_res, &h->d_D})
         b->free();
     wdd::blas_free(h->blas);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -2765,6 +2768,7 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
         return fail(DD_EINVAL, "nt_override must be 0 or >= 3");
     if (!std::isfinite(o.tau_in)) return fail(DD_EINVAL, "tau_in must be finite");
     if (o.restart < 1 || o.restart > 400) return fail(DD_EINVAL, "restart must be in [1, 400]");
+    if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
     const int P = degree;
     const int64_t Nx = (int64_t)box->nx * P + 1, Ny = (int64_t)box->ny * P + 1,
                   Nz = (int64_t)box->nz * P + 1;
@@ -2841,7 +2845,8 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
     }
     h->tab_len = (int64_t)kap.size();
     h->nt_max = *std::max_element(h->nt.begin(), h->nt.end());
-    if (wdd::sweep3_lds_bytes(nxl, nyl, nzl, P, h->nt_max, real3(h)) > kLdsLimit)
+    // FP32 handles also run FP64 refinement sweeps (8-byte LDS grid)
+    if (wdd::sweep3_lds_bytes(nxl, nyl, nzl, P, h->nt_max, 8) > kLdsLimit)
         return fail(DD_EINVAL, "subdomain %dx%dx%d nodes (P=%d, N_t=%d) exceeds the LDS", nxl,
                     nyl, nzl, P, h->nt_max);
 
@@ -2974,6 +2979,14 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
     for (int i = 0; i < 5; ++i) CHK(upload_as(h, h->d_coef.p + i * nn * rs, *coefs[i]));
     const std::vector<double>* tabs[4] = {&kap, &kaph, &cs, &sn};
     for (int i = 0; i < 4; ++i) CHK(upload_as(h, h->d_tab.p + i * h->tab_len * rs, *tabs[i]));
+    if (o.precision == DD_FP32 && o.refine > 0) {
+        HIPCHK(h->d_coef64.alloc(5 * nn * 8));
+        HIPCHK(h->d_tab64.alloc(4 * h->tab_len * 8));
+        for (int i = 0; i < 5; ++i)
+            CHK(upload_real<double>(h->d_coef64.p + i * nn * 8, *coefs[i]));
+        for (int i = 0; i < 4; ++i)
+            CHK(upload_real<double>(h->d_tab64.p + i * h->tab_len * 8, *tabs[i]));
+    }
     std::vector<double> w1d;
     w1d.insert(w1d.end(), wx.begin(), wx.end());
     w1d.insert(w1d.end(), wy.begin(), wy.end());
@@ -2995,8 +3008,10 @@ wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, const double2* gi, double
                                   bool with_f, double tau, int max_wh) {
     wdd::Sweep3Args<Real> a{};
     const int64_t nn = h->L * h->nloc;
-    const Real* coef = reinterpret_cast<const Real*>(h->d_coef.p);
-    const Real* tab = reinterpret_cast<const Real*>(h->d_tab.p);
+    // FP64 sweeps of an FP32 handle read the FP64 copies
+    const bool copy64 = sizeof(Real) == 8 && h->opt.precision == DD_FP32;
+    const Real* coef = reinterpret_cast<const Real*>(copy64 ? h->d_coef64.p : h->d_coef.p);
+    const Real* tab = reinterpret_cast<const Real*>(copy64 ? h->d_tab64.p : h->d_tab.p);
     a.desc = h->d_desc.p;
     a.n_items = (int)h->L;
     a.nxl = h->nxl;
@@ -3040,11 +3055,14 @@ wdd::Sweep3Args<Real> sweep3_args(const dd3_handle* h, const double2* gi, double
 // One launch over all box subdomains (g_in -> g_out); optionally timed with
 // events.  Accumulates the WaveHoltz counts of the launch.
 int run_sweep3_io(dd3_handle* h, const double2* gi, double2* go, double src, bool with_f,
-                  double tau, int max_wh, float* ms) {
+                  double tau, int max_wh, float* ms, int prec = -1) {
     const int wg = (int)(((h->nloc + 63) / 64) * 64);
+    if (prec < 0) prec = h->opt.precision;
+    if (prec == DD_FP64 && h->opt.precision == DD_FP32 && !h->d_coef64.p)
+        return fail(DD_EINVAL, "FP64 sweeps of an FP32 box handle need refine > 0");
     if (ms) HIPCHK(hipEventRecord(h->ev0, h->stream));
     hipError_t e;
-    if (h->opt.precision == DD_FP32)
+    if (prec == DD_FP32)
         e = wdd::launch_sweep3<float>(sweep3_args<float>(h, gi, go, src, with_f, tau, max_wh), wg,
                                       h->stream);
     else
@@ -3084,6 +3102,8 @@ int ensure_solver3(dd3_handle* h) {
     HIPCHK(h->d_ug.alloc(h->N));
     HIPCHK(h->d_Su.alloc(h->N));
     HIPCHK(h->d_work.alloc(h->N));
+    HIPCHK(h->d_res.alloc(h->n_if));
+    HIPCHK(h->d_D.alloc(h->n_if));
     HIPCHK(wdd::blas_init(h->blas, m + 2, h->stream));
     return DD_OK;
 }
@@ -3291,10 +3311,19 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
     h->dof_updates = 0.0;
     const double tau = std::max(h->opt.tau_in, 0.0);
     const int mwh = h->opt.max_wh;
+    // FP64 iterative refinement for FP32 handles (the 2D reading of the
+    // reduced-precision outer iteration): residuals r = h - (I - T) G from
+    // FP64 sweeps, corrections G += GMRES((I - T) d = r) with FP32 sweeps.
+    // An FP64 handle (or refine = 0) runs one pass: plain GMRES from G = 0.
+    const bool fp32 = h->opt.precision == DD_FP32;
+    const bool refine = fp32 && h->opt.refine > 0;
+    const int rprec = refine ? DD_FP64 : h->opt.precision;
+    const double rtau = refine ? std::min(1e-8, std::max(1e-13, 0.01 * tol)) : tau;
+    const int passes = refine ? 1 + h->opt.refine : 1;
     // h = sweep(0, sources on): the affine part of the sweep map (no outer
     // boundary data in the box problem)
     HIPCHK(hipMemsetAsync(h->d_tmp.p, 0, sizeof(double2) * h->n_if, h->stream));
-    CHK(run_sweep3_io(h, h->d_tmp.p, h->d_h.p, 1.0, with_f, tau, mwh, nullptr));
+    CHK(run_sweep3_io(h, h->d_tmp.p, h->d_h.p, 1.0, with_f, rtau, mwh, nullptr, rprec));
     Krylov K{};
     K.blas = &h->blas;
     K.stream = h->stream;
@@ -3312,14 +3341,42 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
     K.tau_strict = tau;
     const double hn = knorm(K, h->d_h.p);
     if (!std::isfinite(hn)) return fail(DD_ENAN, "non-finite interface data");
-    int its = 0;
-    double rel = 0.0;
-    CHK(gmres_core(K, h->d_h.p, h->d_G.p, hn, tol, max_iter, &its, &rel));
-    // u from the final sweep of G with sources on (g_fin = T G + h), glued
-    // to the global nodes; true interface residual ||g_fin - G|| / ||h||
-    CHK(run_sweep3_io(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, tau, mwh, nullptr));
-    CHK(kaxpby(K, cplx(-1.0), h->d_G.p, cplx(1.0), h->d_tmp.p));
-    const double rtrue = hn > 0.0 ? knorm(K, h->d_tmp.p) / hn : 0.0;
+    HIPCHK(hipMemsetAsync(h->d_G.p, 0, sizeof(double2) * h->n_if, h->stream));
+    HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_h.p, sizeof(double2) * h->n_if,
+                          hipMemcpyDeviceToDevice, h->stream));
+    int its = 0, steps = 0;
+    double rnorm = hn, rtrue = hn > 0.0 ? 1.0 : 0.0, last_rec = rtrue;
+    bool have_u = false;
+    for (int k = 0; k < passes && rtrue > tol && its < max_iter; ++k) {
+        // FP32 corrections under refinement aim at a fixed reduction (their
+        // operator is only FP32-accurate); a single pass goes the whole way
+        const double want = tol * hn / rnorm;
+        const double inner = refine ? std::max(1e-4, want) : want;
+        int pits = 0;
+        double irel = 0.0;
+        CHK(gmres_core(K, h->d_res.p, h->d_D.p, rnorm, inner, max_iter - its, &pits, &irel));
+        its += pits;
+        last_rec = irel * rnorm / hn;
+        CHK(kaxpby(K, cplx(1.0), h->d_D.p, cplx(1.0), h->d_G.p));
+        // true residual and u from the sweep of G with sources on:
+        // g_fin = T G + h, r = g_fin - G
+        CHK(run_sweep3_io(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, rtau, mwh, nullptr, rprec));
+        CHK(kaxpby(K, cplx(-1.0), h->d_G.p, cplx(1.0), h->d_tmp.p));
+        rnorm = knorm(K, h->d_tmp.p);
+        if (!std::isfinite(rnorm)) return fail(DD_ENAN, "non-finite outer residual");
+        rtrue = hn > 0.0 ? rnorm / hn : 0.0;
+        HIPCHK(hipMemcpyAsync(h->d_res.p, h->d_tmp.p, sizeof(double2) * h->n_if,
+                              hipMemcpyDeviceToDevice, h->stream));
+        steps = k + 1;
+        have_u = true;
+    }
+    if (!have_u) {
+        // nothing to correct (h = 0): u from the sweep of G = 0
+        CHK(run_sweep3_io(h, h->d_G.p, h->d_tmp.p, 1.0, with_f, rtau, mwh, nullptr, rprec));
+        rtrue = 0.0;
+        last_rec = 0.0;
+    }
+    double rel = std::max(last_rec, rtrue);
     HIPCHK(wdd::launch_glue3(op3_args(h), h->d_u.p, h->mx, h->my, h->mz, h->part.sx, h->part.sy,
                              h->part.sz, h->d_ug.p, h->stream));
     std::vector<double2> u(h->N);
@@ -3330,11 +3387,11 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
         u_re[i] = u[i].x;
         u_im[i] = u[i].y;
     }
-    rel = std::max(rel, rtrue);
     if (!std::isfinite(rel)) return fail(DD_ENAN, "non-finite outer residual");
     if (st) {
         *st = dd_stats{};
         st->outer_iters = its;
+        st->refine_steps = refine ? steps : 0;
         st->sweeps = (int)h->sweeps;
         st->rel_residual = rel;
         st->true_rel_residual = rtrue;

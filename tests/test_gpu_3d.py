@@ -295,12 +295,12 @@ def test_solve_tight_matches_global_lu(gpu_lib):
     assert rel_res < 1e-10
 
 
-def test_solve_fp32_sweeps(gpu_lib):
-    """FP32 box sweeps under the FP64 outer GMRES reach the answer to the
-    FP32 sweep accuracy (no refinement in the box solve)."""
+def test_solve_fp32_sweeps_plain(gpu_lib):
+    """FP32 box sweeps under the FP64 outer GMRES without refinement reach
+    the answer to the FP32 sweep accuracy."""
     W = gpu_lib
     shape, om = (4, 4, 4, 2, 2, 2, 2), 6.0
-    h, Xl, Yl, Zl = _setup(W, shape, om, precision=1, tau_in=1e-6, max_wh=400)
+    h, Xl, Yl, Zl = _setup(W, shape, om, precision=1, tau_in=1e-6, max_wh=400, refine=0)
     mesh = sem3.Box(*shape[:4], *BOX)
     X, Y, Z = sem3.node_coords(mesh)
     u, st, rc = W.dd3_solve(h, _src(Xl, Yl, Zl), 1e-5, allow_notconv=True)
@@ -350,3 +350,24 @@ def test_solve_zero_source_and_bad_arguments(gpu_lib):
         W.dd3_solve(h, f, 1e-8)
     assert ei.value.code == W.DD_ENAN
     W.dd3_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4, 2, 2, 2, 2), (3, 2, 4, 3, 3, 1, 2)])
+def test_solve_fp32_refined_matches_fp64(gpu_lib, shape):
+    """FP32 box sweeps with FP64 iterative refinement: the same outer
+    tolerance as the FP64 oracle DD, and the answer within 1e-6 of it."""
+    from oracle import dd
+    W = gpu_lib
+    om, tol = 6.0, 1e-8
+    h, Xl, Yl, Zl = _setup(W, shape, om, precision=1, tau_in=1e-6, max_wh=400)
+    u, st, rc = W.dd3_solve(h, _src(Xl, Yl, Zl), tol)
+    W.dd3_destroy(h)
+    dec, X, Y, Z = _oracle(shape, om)
+    us_ref, info = dd.solve_dd(dec, _src(X, Y, Z), tol=tol)
+    err = _rel([u], [dec.glue(us_ref)])
+    print(f"box fp32 refined rc={rc} iters={st['outer_iters']} refine={st['refine_steps']} "
+          f"true={st['true_rel_residual']:.2e} err={err:.2e}", flush=True)
+    assert rc == 0 and st["true_rel_residual"] <= tol
+    assert st["refine_steps"] >= 2
+    assert err < 1e-6
+
