@@ -494,7 +494,7 @@ def box_solve_bench(args, W, wl, h, X, Y, Z, s):
     # FP32 WaveHoltz stagnates near 1e-6, so FP32 sweeps take 1e-5 (the FP64
     # refinement sweeps use their own tolerance)
     tau = 1e-12 if prec == W.DD_FP64 else 1e-5
-    o = W.dd_default_options(precision=prec, tau_in=tau, max_wh=1000)
+    o = W.dd_default_options(precision=prec, tau_in=tau, max_wh=1000, relax=args.relax)
     h = W.dd3_setup(wl.nx, wl.ny, wl.nz, wl.P, wl.c(X, Y, Z), wl.omega, wl.sx, wl.sy, wl.sz,
                     *wl.box, options=o)
     f = wl.f(X, Y, Z)
@@ -513,7 +513,8 @@ def box_solve_bench(args, W, wl, h, X, Y, Z, s):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": args.precision.replace("fp", "f"), "data": "synthetic (workload source)",
            "config": {"workload": f"{args.config}: {wl.nx}x{wl.ny}x{wl.nz} elements P={wl.P}, "
-                                  f"{wl.sx}x{wl.sy}x{wl.sz} subdomains, tol={tol}, tau_in={tau}"},
+                                  f"{wl.sx}x{wl.sy}x{wl.sz} subdomains, tol={tol}, tau_in={tau}",
+                      "relax": args.relax},
            "outer_iters": st["outer_iters"], "converged": rc == 0,
            "true_rel_residual_interface": st["true_rel_residual"],
            "rel_residual_global_fp64": rel, "wh_iters_max": st["wh_iters_max"],

@@ -30,9 +30,9 @@
  *   writes 0 there.
  *
  * Options: dd_options from wavedd.h; precision, tau_in, max_wh, cfl,
- * nt_override, restart and refine are used (tau_in <= 0 runs exactly max_wh
- * WaveHoltz iterations); the outer method is always GMRES, and the layout,
- * relax, warm-start and tc2 fields are ignored.  Errors, threading and
+ * nt_override, restart, refine and relax are used (tau_in <= 0 runs
+ * exactly max_wh WaveHoltz iterations); the outer method is always GMRES,
+ * and the layout, warm-start and tc2 fields are ignored.  Errors, threading and
  * memory ownership as in wavedd.h.
  */
 #ifndef WAVEDD3_H
@@ -103,7 +103,10 @@ int dd3_time_sweep(dd3_handle* h, int reps, int fixed_iters, double* ms, double*
  * operator) run FP64 iterative refinement: h, the residuals
  * r = h - (I - T) G and u come from FP64 sweeps (WaveHoltz tolerance
  * clamp(0.01 tol, 1e-13, 1e-8)), the corrections G += GMRES((I - T) d = r)
- * from FP32 sweeps, at most `refine` extra corrections.  u is the sweep of
+ * from FP32 sweeps, at most `refine` extra corrections.  relax > 0 makes
+ * the GMRES matvec tolerance variable, clamp(relax tol / rel_k, tau_in,
+ * 1e-2) (inexact Krylov), with FP64 refinement passes for FP64 handles too
+ * (residual sweeps at tau_in).  u is the sweep of
  * the converged G, glued at the global nodes (mean of the subdomain
  * copies).  u_re, u_im: N host values.  st (may be NULL): outer
  * iterations, sweeps, refine_steps, rel_residual = max(GMRES estimate,

@@ -2769,6 +2769,7 @@ int prepare3(dd3_handle* h, const dd_box* box, int degree, const double* c, doub
     if (!std::isfinite(o.tau_in)) return fail(DD_EINVAL, "tau_in must be finite");
     if (o.restart < 1 || o.restart > 400) return fail(DD_EINVAL, "restart must be in [1, 400]");
     if (o.refine < 0 || o.refine > 50) return fail(DD_EINVAL, "refine must be in [0, 50]");
+    if (!(o.relax >= 0.0) || !std::isfinite(o.relax)) return fail(DD_EINVAL, "relax must be >= 0");
     const int P = degree;
     const int64_t Nx = (int64_t)box->nx * P + 1, Ny = (int64_t)box->ny * P + 1,
                   Nz = (int64_t)box->nz * P + 1;
@@ -3311,15 +3312,18 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
     h->dof_updates = 0.0;
     const double tau = std::max(h->opt.tau_in, 0.0);
     const int mwh = h->opt.max_wh;
-    // FP64 iterative refinement for FP32 handles (the 2D reading of the
-    // reduced-precision outer iteration): residuals r = h - (I - T) G from
-    // FP64 sweeps, corrections G += GMRES((I - T) d = r) with FP32 sweeps.
-    // An FP64 handle (or refine = 0) runs one pass: plain GMRES from G = 0.
+    // FP64 iterative refinement (the 2D reading of the reduced-precision
+    // outer iteration): residuals r = h - (I - T) G from FP64 sweeps,
+    // corrections G += GMRES((I - T) d = r) with sweeps in the handle's
+    // precision and, with relax > 0, a variable inner tolerance.  A strict
+    // FP64 solve finishes in the first pass (plain GMRES from G = 0).
     const bool fp32 = h->opt.precision == DD_FP32;
-    const bool refine = fp32 && h->opt.refine > 0;
+    const bool refine = h->opt.refine > 0 && (fp32 || h->opt.relax > 0.0);
+    const bool fp32_refined = fp32 && refine;
     const int rprec = refine ? DD_FP64 : h->opt.precision;
-    const double rtau = refine ? std::min(1e-8, std::max(1e-13, 0.01 * tol)) : tau;
+    const double rtau = fp32_refined ? std::min(1e-8, std::max(1e-13, 0.01 * tol)) : tau;
     const int passes = refine ? 1 + h->opt.refine : 1;
+    const double relax = h->opt.relax;
     // h = sweep(0, sources on): the affine part of the sweep map (no outer
     // boundary data in the box problem)
     HIPCHK(hipMemsetAsync(h->d_tmp.p, 0, sizeof(double2) * h->n_if, h->stream));
@@ -3337,7 +3341,12 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
         CHK(run_sweep3_io(h, v, w, 0.0, false, t, mwh, nullptr));
         return kaxpby(Krylov{&h->blas, h->stream, h->n_if}, cplx(1.0), v, cplx(-1.0), w);
     };
-    K.tau = [tau](double) { return tau; };
+    // inexact Krylov: the matvec tolerance may grow as 1 / (residual),
+    // tau_k = clamp(relax * tol / rel_k, tau_in, 1e-2) (relax = 0: tau_in)
+    K.tau = [tau, relax, tol](double rel) {
+        if (!(relax > 0.0)) return tau;
+        return std::min(1e-2, std::max(tau, relax * tol / std::max(rel, 1e-300)));
+    };
     K.tau_strict = tau;
     const double hn = knorm(K, h->d_h.p);
     if (!std::isfinite(hn)) return fail(DD_ENAN, "non-finite interface data");
@@ -3351,7 +3360,7 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
         // FP32 corrections under refinement aim at a fixed reduction (their
         // operator is only FP32-accurate); a single pass goes the whole way
         const double want = tol * hn / rnorm;
-        const double inner = refine ? std::max(1e-4, want) : want;
+        const double inner = fp32_refined ? std::max(1e-4, want) : want;
         int pits = 0;
         double irel = 0.0;
         CHK(gmres_core(K, h->d_res.p, h->d_D.p, rnorm, inner, max_iter - its, &pits, &irel));
@@ -3391,7 +3400,7 @@ int dd3_solve(dd3_handle* h, const double* f_re, const double* f_im, double tol,
     if (st) {
         *st = dd_stats{};
         st->outer_iters = its;
-        st->refine_steps = refine ? steps : 0;
+        st->refine_steps = refine ? steps : 0;  // passes with an FP64 residual
         st->sweeps = (int)h->sweeps;
         st->rel_residual = rel;
         st->true_rel_residual = rtrue;

@@ -371,3 +371,26 @@ def test_solve_fp32_refined_matches_fp64(gpu_lib, shape):
     assert st["refine_steps"] >= 2
     assert err < 1e-6
 
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_relaxed_inner_tolerance(gpu_lib, prec):
+    """Variable inner tolerance (relax = 0.1) with FP64 refinement: the same
+    answer as the strict FP64 solve at the outer tolerance, with fewer
+    WaveHoltz iterations."""
+    W = gpu_lib
+    shape, om, tol = (4, 4, 4, 2, 2, 2, 2), 6.0, 1e-8
+    h, Xl, Yl, Zl = _setup(W, shape, om, tau_in=1e-12, max_wh=400)
+    u0, st0, _ = W.dd3_solve(h, _src(Xl, Yl, Zl), tol)
+    W.dd3_destroy(h)
+    tau = 1e-12 if prec == 0 else 1e-5
+    h, Xl, Yl, Zl = _setup(W, shape, om, precision=prec, tau_in=tau, max_wh=400, relax=0.1)
+    u, st, rc = W.dd3_solve(h, _src(Xl, Yl, Zl), tol)
+    W.dd3_destroy(h)
+    print(f"box relax prec={prec} rc={rc} iters={st['outer_iters']} refine={st['refine_steps']} "
+          f"wh={st['wh_iters_total']} vs strict {st0['wh_iters_total']} diff={_rel([u], [u0]):.2e}",
+          flush=True)
+    assert rc == 0 and st["true_rel_residual"] <= tol
+    assert _rel([u], [u0]) < 1e-6
+    if prec == 0:
+        assert st["wh_iters_total"] < st0["wh_iters_total"]
