@@ -211,21 +211,23 @@ def test_c6_small_protocol_sweep(gpu_lib, prec):
     assert _rel([g_gpu], [g_ref]) < tol
 
 
+@pytest.mark.parametrize("name", ["c6", "c6_p1"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_c6_full_size_sweep_sampled(gpu_lib, prec):
-    """The full c6 launch (64^3 elements, 32768 subdomains, the bench's
-    configuration) checked on sampled subdomains: each sampled subdomain's
-    WaveHoltz iterate equals the oracle's on that subdomain alone (a
-    one-subdomain decomposition of its box with its slice of g), and the
-    interface data it sends to every neighbour equals -g - 2i(omega/c)u."""
+def test_c6_full_size_sweep_sampled(gpu_lib, prec, name):
+    """The full box launches of the bench (c6: 64^3 elements, P=3, 32768
+    subdomains; c6_p1: 128^3 elements, P=1, 4096 subdomains) checked on
+    sampled subdomains: each sampled subdomain's WaveHoltz iterate equals
+    the oracle's on that subdomain alone (a one-subdomain decomposition of
+    its box with its slice of g), and the interface data it sends to every
+    neighbour equals -g - 2i(omega/c)u."""
     import workloads
     W = gpu_lib
-    wl = workloads.c6()
+    wl = workloads.CONFIGS3[name]()
     h, Xl, Yl, Zl = _box_workload_setup(W, wl, prec, 5)
     s = W.dd3_sizes(h)
     rng = np.random.default_rng(66)
     g = rng.standard_normal(s["n_iface"]) + 1j * rng.standard_normal(s["n_iface"])
-    print(f"c6 full-size sweep prec={prec}", flush=True)
+    print(f"{name} full-size sweep prec={prec}", flush=True)
     g_gpu, u_gpu, its = W.dd3_sweep(h, g, wl.f(Xl, Yl, Zl), 1.0)
     W.dd3_destroy(h)
     assert (its == 5).all()
