@@ -92,6 +92,86 @@ def flops_per_update(P):
     return 4 * (P + 2) + 16
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, logical CPUs, the CPUs this
+    process may use, memory."""
+    info = {"cpu_model": None, "nproc": os.cpu_count(), "ram_gib": None}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity_cpus"] = os.cpu_count()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    info["ram_gib"] = round(int(line.split()[1]) / (1 << 20), 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def oracle_setup(wl):
+    """The oracle's mesh, node coordinates, wavespeed and source of a 2D
+    workload (sampled at the oracle's own node coordinates)."""
+    from oracle import sem
+    mesh = sem.Rect(wl.nx, wl.ny, wl.P, wl.x0, wl.x1, wl.y0, wl.y1)
+    X, Y = sem.node_coords(mesh)
+    return mesh, wl.c(X, Y), wl.f(X, Y)
+
+
+def cpu_baseline_dd(wl, tol, workers=None):
+    """The oracle DD (exact sparse-LU subdomain solves, the same restarted
+    GMRES from G = 0, the same outer tolerance) on a pool of host processes,
+    one BLAS thread each: subdomain factorisation time, then one full solve
+    timed.  Returns (baseline dict, glued oracle solution)."""
+    from oracle import dd, pool
+    mesh, c, f = oracle_setup(wl)
+    t0 = time.perf_counter()
+    pdec = pool.ParallelDecomposition(mesh, dd.Partition(wl.sx, wl.sy), c, wl.omega,
+                                      workers=workers)
+    try:
+        pdec.factor()
+        setup_s = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        us, info = dd.solve_dd(pdec, f, tol=tol)
+        solve_s = time.perf_counter() - t1
+        u = pdec.glue(us)
+        n = pdec.workers
+    finally:
+        pdec.close()
+    base = {"value": 1.0 / solve_s, "unit": "solves/s", "cores": n, "kind": "oracle",
+            "sample": f"one oracle-DD solve of the same workload ({wl.sx * wl.sy} sparse-LU "
+                      f"subdomain solves per sweep on {n} worker processes, one BLAS thread "
+                      f"each, restarted GMRES(50) from G = 0 to tol {tol}): {solve_s:.1f} s, "
+                      f"{info['iters']} outer iterations; subdomain factorisation "
+                      f"{setup_s:.1f} s not counted",
+            "solve_s": solve_s, "factor_s": setup_s, "outer_iters": info["iters"],
+            "true_rel_residual_interface": info["true_rel"], **host_info()}
+    return base, u
+
+
+def cpu_global_lu(wl):
+    """Global sparse LU of S = A - i omega H - omega^2 M (SuperLU, one
+    thread): factorisation and solve times and the solution."""
+    import scipy.sparse.linalg as spla
+    from oracle import sem
+    mesh, c, f = oracle_setup(wl)
+    S, _, _, _ = sem.system(mesh, c, wl.omega)
+    b = sem.load(mesh, f)
+    t0 = time.perf_counter()
+    lu = spla.splu(S)
+    t1 = time.perf_counter()
+    u = lu.solve(b)
+    t2 = time.perf_counter()
+    return {"n": int(S.shape[0]), "factor_s": t1 - t0, "solve_s": t2 - t1}, u
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The oracle's WaveHoltz (vectorised numpy, FP64) on this workload's
     subdomains, one WaveHoltz iteration per subdomain, subdomains taken in
@@ -161,22 +241,50 @@ def cpu_baseline3(wl, seconds=12.0, n_sub=8):
                       f"numpy/scipy FP64, one thread ({el:.1f} s)"}
 
 
-# name: (sweep precision, inner tolerance (None: the workload's), relax, tc2)
-VARIANTS = {"fp32_refined": ("fp32", 1e-6, 0.0, 0.0), "fp64_relaxed": ("fp64", None, 0.1, 0.0),
-            "fp32_refined_relaxed": ("fp32", 1e-6, 0.1, 0.0),
+# name: (sweep precision, inner tolerance (None: the workload's), relax, tc2).
+# FP32 WaveHoltz stagnates near 1e-6, so FP32 sweeps stop at 1e-5 and the
+# FP64 refinement sweeps (the workload's tolerance) carry the accuracy.
+VARIANTS = {"fp32_refined": ("fp32", 1e-5, 0.0, 0.0), "fp64_relaxed": ("fp64", None, 0.1, 0.0),
+            "fp32_refined_relaxed": ("fp32", 1e-5, 0.1, 0.0),
             "fp64_tc2": ("fp64", None, 0.0, 0.1),
-            "fp32_refined_relaxed_tc2": ("fp32", 1e-6, 0.1, 0.1)}
+            "fp32_refined_relaxed_tc2": ("fp32", 1e-5, 0.1, 0.1)}
 
 
-def variants(W, wl, u_ref, names, max_wh, progress=0, steps=2):
+def rel_l2(u, ref):
+    """Relative l2 difference of glued nodal vectors."""
+    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+
+
+def timed_solves(W, prob, tol, steps, warmup=1, max_iter=2000):
+    """`warmup` untimed then `steps` timed dd_solve_device calls with the
+    source resident in HBM; a solve that does not converge raises.  Returns
+    (per-solve seconds, stats of each, solution of the last)."""
+    import torch
+    dev = torch.device("cuda:0")
+    N = prob.f.size
+    f_re = torch.from_numpy(prob.f).to(dev)
+    u_re = torch.empty(N, dtype=torch.float64, device=dev)
+    u_im = torch.empty(N, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        W.dd_solve_device(prob.h, f_re, None, None, None, tol, max_iter, u_re, u_im)
+    torch.cuda.synchronize()
+    lat, stats = [], []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        st, _ = W.dd_solve_device(prob.h, f_re, None, None, None, tol, max_iter, u_re, u_im)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+        stats.append(st)
+    u = u_re.cpu().numpy() + 1j * u_im.cpu().numpy()
+    return lat, stats, u
+
+
+def variants(W, wl, names, max_wh, progress=0, steps=2):
     """FP32 sweeps (with FP64 refinement), relaxed inner tolerance and the
     second-order transmission condition on the same workload: solves/s,
-    latency, DOF-updates/s and the relative L2 difference from the main
-    run's solution."""
-    import torch
-    out = {}
-    N = u_ref.size
-    dev = torch.device("cuda:0")
+    latency, DOF-updates/s; returns the results and each variant's
+    solution (compared with the oracle by the caller)."""
+    out, sols = {}, {}
     for name in names:
         pname, tau, relax, tc2 = VARIANTS[name]
         prec = W.DD_FP64 if pname == "fp64" else W.DD_FP32
@@ -185,32 +293,44 @@ def variants(W, wl, u_ref, names, max_wh, progress=0, steps=2):
         if progress:
             W.dd_set_progress(prob.h, lambda it, rel, n=name: log(f"  {n} outer {it}: {rel:.2e}"),
                               progress)
-        f_re = torch.from_numpy(prob.f).to(dev)
-        u_re = torch.empty(N, dtype=torch.float64, device=dev)
-        u_im = torch.empty(N, dtype=torch.float64, device=dev)
-        W.dd_solve_device(prob.h, f_re, None, None, None, wl.tol, 2000, u_re, u_im,
-                          allow_notconv=True)
-        torch.cuda.synchronize()
-        lat, dof, st = [], 0.0, None
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            t1 = time.perf_counter()
-            st, rc = W.dd_solve_device(prob.h, f_re, None, None, None, wl.tol, 2000, u_re, u_im,
-                                       allow_notconv=True)
-            lat.append(time.perf_counter() - t1)
-            dof += st["dof_updates"]
-        total = time.perf_counter() - t0
-        u = u_re.cpu().numpy() + 1j * u_im.cpu().numpy()
-        out[name] = {"solves_per_s": steps / total, "dof_updates_per_s": dof / total,
+        lat, stats, u = timed_solves(W, prob, wl.tol, steps)
+        total = sum(lat)
+        st = stats[-1]
+        out[name] = {"solves_per_s": steps / total,
+                     "dof_updates_per_s": sum(x["dof_updates"] for x in stats) / total,
                      "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                     "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                     "p99_ms": 1e3 * float(np.percentile(lat, 99)), "solves_timed": steps,
                      "outer_iters": st["outer_iters"], "refine_steps": st["refine_steps"],
+                     "wh_iters_max": st["wh_iters_max"],
                      "true_rel_residual_interface": st["true_rel_residual"],
-                     "rel_l2_vs_fp64": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
                      "rel_residual_global_fp64": W.dd_residual(prob.h, u, prob.f),
                      "tau_in": tau, "relax": relax, "tc2": tc2}
+        sols[name] = u
+        log(f"variant {name}: {1e3 * total / steps:.0f} ms per solve, "
+            f"{st['outer_iters']} outer iterations")
         prob.close()
-    return out
+    return out, sols
+
+
+def c1_latency(W, steps=20):
+    """The 16x16-element, P=2, 2x2-subdomain problem: latency of single
+    solves (FP64, and FP32 sweeps with FP64 refinement) and of one sweep;
+    returns the results and the solutions."""
+    import workloads
+    wl = workloads.c1()
+    out, sols = {}, {}
+    for name, prec, tau in (("fp64", W.DD_FP64, wl.tau_in), ("fp32_refined", W.DD_FP32, 1e-5)):
+        prob = W.Problem(wl, precision=prec, tau_in=tau, max_wh=1000)
+        lat, stats, u = timed_solves(W, prob, wl.tol, steps, warmup=3)
+        st = stats[-1]
+        out[name] = {"us_per_solve_p50": 1e6 * float(np.percentile(lat, 50)),
+                     "us_per_solve_p99": 1e6 * float(np.percentile(lat, 99)),
+                     "us_per_sweep": 1e6 * st["sweep_seconds"] / max(st["sweeps"], 1),
+                     "sweeps_per_solve": st["sweeps"], "outer_iters": st["outer_iters"],
+                     "solves_timed": steps, "tau_in": tau}
+        sols[name] = u
+        prob.close()
+    return out, sols
 
 
 BYTES_STREAM = {"fp64": 80, "fp32": 40}   # per DOF-update, STREAM layout (10 words)
@@ -607,6 +727,10 @@ def main():
     ap.add_argument("--tc2", type=float, default=0.0,
                     help="second-order transmission condition (0 = the paper's zeroth order)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the 16x16-element latency solves of the default run")
+    ap.add_argument("--global-lu", action="store_true",
+                    help="also time the oracle's global sparse LU of the workload")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / relaxed-tolerance comparison solves")
     ap.add_argument("--variants", default=None,
@@ -616,10 +740,10 @@ def main():
                     help="print the outer residual every N iterations (default: 25 for "
                          "512x512, off otherwise)")
     ap.add_argument("--serve", action="store_true", help="serving engine on the c5 stream")
-    ap.add_argument("--max-wh", type=int, default=None,
-                    help="WaveHoltz cap per subdomain solve (default: the library's 100 for "
-                         "the 256x256 workloads, 1000 for the 512x512, batch and serving "
-                         "workloads, whose large subdomains need hundreds of periods)")
+    ap.add_argument("--max-wh", type=int, default=1000,
+                    help="WaveHoltz cap per subdomain solve (a safety limit: the stop rule "
+                         "is the inner tolerance; the 256x256 waveguide needs up to 135 "
+                         "periods, the 64-element subdomains of the larger workloads hundreds)")
     ap.add_argument("--protocol", action="store_true",
                     help="the paper's DD-cycle timing instead of solves: sweeps of exactly 5 "
                          "WaveHoltz iterations per subdomain on random interface data")
@@ -651,8 +775,6 @@ def main():
         a.copy_(b)
         torch.cuda.synchronize()
         del a, b
-    if args.max_wh is None:
-        args.max_wh = 100 if args.config in ("c1", "c2", "c2_small", "c2_t1") and not args.serve else 1000
     if args.serve:
         return serve_bench(args)
     if args.config.startswith("c6"):
@@ -669,7 +791,7 @@ def main():
     torch.cuda.set_device(0)
     wl = workloads.CONFIGS[args.config]()
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
-    tau = wl.tau_in if prec == W.DD_FP64 else max(wl.tau_in, 1e-6)
+    tau = wl.tau_in if prec == W.DD_FP64 else max(wl.tau_in, 1e-5)
     if args.tau_in is not None:
         tau = args.tau_in
     t0 = time.perf_counter()
@@ -681,32 +803,11 @@ def main():
     if args.progress:
         W.dd_set_progress(prob.h, lambda it, rel: log(f"  outer {it}: {rel:.2e}"), args.progress)
     h = prob.h
-    sizes = W.dd_sizes(h)
-    N = sizes["n_global"]
-    dev = torch.device("cuda:0")
-    f_re = torch.from_numpy(prob.f).to(dev)
-    u_re = torch.empty(N, dtype=torch.float64, device=dev)
-    u_im = torch.empty(N, dtype=torch.float64, device=dev)
-
-    def one():
-        st, rc = W.dd_solve_device(h, f_re, None, None, None, wl.tol, 2000, u_re, u_im,
-                                   allow_notconv=True)
-        return st
-
     log(f"setup {setup_s:.1f} s, layout {W.dd_layout(h)}")
-    for _ in range(args.warmup):
-        one()
-        log("warm-up solve done")
-    torch.cuda.synchronize()
-    lat, stats = [], []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        t1 = time.perf_counter()
-        stats.append(one())
-        lat.append(time.perf_counter() - t1)
-        log(f"solve {k}: {lat[-1]:.3f} s, {stats[-1]['outer_iters']} outer iterations")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
+    lat, stats, u = timed_solves(W, prob, wl.tol, args.steps, warmup=args.warmup)
+    for k, (t, st) in enumerate(zip(lat, stats)):
+        log(f"solve {k}: {t:.3f} s, {st['outer_iters']} outer iterations")
+    total = sum(lat)
 
     dof = sum(s["dof_updates"] for s in stats)
     sweeps = sum(s["sweeps"] for s in stats)
@@ -716,7 +817,6 @@ def main():
     achieved = fl * dof / sweep_s / 1e12 if sweep_s > 0 else 0.0
     peak = PEAK_TFLOPS[args.precision]
     lay, wg = W.dd_layout(h)
-    u = (u_re.cpu().numpy() + 1j * u_im.cpu().numpy())
     rel_res = W.dd_residual(h, u, prob.f)
     nt = W.dd_time_steps(h)
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -751,10 +851,12 @@ def main():
         "outer_iters": stats[-1]["outer_iters"],
         "sweeps_per_solve": stats[-1]["sweeps"],
         "wh_iters_max": stats[-1]["wh_iters_max"],
+        "wh_iters_mean": stats[-1]["wh_iters_total"] / (stats[-1]["sweeps"] * wl.sx * wl.sy),
         "nt_range": [int(nt.min()), int(nt.max())],
         "sweep_fraction_of_time": sweep_s / total,
         "rel_residual_global_fp64": rel_res,
         "true_rel_residual_interface": stats[-1]["true_rel_residual"],
+        "rel_l2_vs_oracle": None,
         "setup_s": setup_s,
         "roofline": dict(roof, **{
             "traffic": MEASURED_TRAFFIC.get((kernel_hash(lay), "solve", args.config,
@@ -763,14 +865,49 @@ def main():
             "flop_per_dof_update": fl,
             "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None}),
     }
+    prob.close()
+    sols = {}
     if not args.no_variants:
         names = (args.variants.split(",") if args.variants else
                  ["fp32_refined_relaxed"] if args.config == "c3" else list(VARIANTS))
-        out["variants"] = variants(W, wl, u, names, args.max_wh, args.progress,
-                                   steps=min(2, args.steps))
+        out["variants"], sols = variants(W, wl, names, args.max_wh, args.progress,
+                                         steps=min(2, args.steps))
+    c1_sols = {}
+    if args.config == "c2" and not args.no_c1:
+        out["c1_latency"], c1_sols = c1_latency(W)
+        log("c1 latency done")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
-    prob.close()
+        # the oracle: DD with exact subdomain solves at the same outer
+        # tolerance on the host's cores; every GPU solution is compared with it
+        log("cpu baseline: oracle DD on a process pool")
+        base, u_ref = cpu_baseline_dd(wl, wl.tol)
+        out["cpu_baseline"] = base
+        out["rel_l2_vs_oracle"] = rel_l2(u, u_ref)
+        for name, uv in sols.items():
+            out["variants"][name]["rel_l2_vs_oracle"] = rel_l2(uv, u_ref)
+        log("cpu baseline: WaveHoltz iterate rate")
+        out["cpu_baseline"]["waveholtz_oracle"] = cpu_baseline(wl, seconds=6.0)
+        if c1_sols:
+            import workloads
+            from oracle import dd
+            wl1 = workloads.c1()
+            mesh1, c_1, f_1 = oracle_setup(wl1)
+            dec1 = dd.Decomposition(mesh1, dd.Partition(wl1.sx, wl1.sy), c_1, wl1.omega)
+            t0 = time.perf_counter()
+            us1, _ = dd.solve_dd(dec1, f_1, tol=wl1.tol)
+            dd_s = time.perf_counter() - t0
+            u1 = dec1.glue(us1)
+            lu1, u1_lu = cpu_global_lu(wl1)
+            for name, uv in c1_sols.items():
+                out["c1_latency"][name]["rel_l2_vs_oracle"] = rel_l2(uv, u1)
+                out["c1_latency"][name]["rel_l2_vs_global_lu"] = rel_l2(uv, u1_lu)
+            out["c1_latency"]["oracle"] = {"dd_solve_s_one_thread": dd_s, "global_lu": lu1}
+        if args.global_lu:
+            log("cpu baseline: global sparse LU")
+            lu, u_lu = cpu_global_lu(wl)
+            lu["rel_l2_gpu_vs_global_lu"] = rel_l2(u, u_lu)
+            lu["rel_l2_oracle_dd_vs_global_lu"] = rel_l2(u_ref, u_lu)
+            out["cpu_baseline"]["global_lu"] = lu
     print(json.dumps(out))
 
 

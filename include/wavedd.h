@@ -141,7 +141,7 @@ typedef struct {
     int fp64_sweeps;            /* FP64 sweeps of a refined FP32 solve */
 } dd_stats;
 
-/* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 100, GMRES(50),
+/* Defaults: FP64, auto layout, tau_in 1e-12, max_wh 1000, GMRES(50),
  * no N_t override, cfl 0.9, refine 4, relax 0, warm 0, tc2 0. */
 int dd_default_options(dd_options* opt);
 

@@ -1027,10 +1027,11 @@ int solve_gmres_refined(dd_handle* h, bool with_f, double tol, int max_iter) {
     double last_rec = rel;
     bool have_u = false;
     for (int k = 0; k < passes && rel > tol && its_total < max_iter; ++k) {
-        // FP32 corrections aim at a fixed reduction (their operator is only
-        // FP32-accurate); FP64 ones go for the whole way
+        // FP32 corrections inside a refinement loop aim at a fixed reduction
+        // (their operator is only FP32-accurate); FP64 ones, and a single
+        // FP32 pass (refine = 0), go for the whole way
         const double want = tol * hnorm / rnorm;
-        const double inner = fp32 ? std::max(1e-4, want) : want;
+        const double inner = (fp32 && passes > 1) ? std::max(1e-4, want) : want;
         int its = 0;
         double irel = 0.0;
         h->prog_base = its_total;
@@ -1712,7 +1713,7 @@ int dd_default_options(dd_options* o) {
     o->precision = DD_FP64;
     o->layout = DD_LAYOUT_AUTO;
     o->tau_in = 1e-12;
-    o->max_wh = 100;
+    o->max_wh = 1000;
     o->outer = DD_OUTER_GMRES;
     o->restart = 50;
     o->nt_override = 0;

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options():
     o = wavedd.dd_default_options()
-    assert o.precision == wavedd.DD_FP64 and o.restart == 50 and o.max_wh == 100
+    assert o.precision == wavedd.DD_FP64 and o.restart == 50 and o.max_wh == 1000
     assert abs(o.cfl - 0.9) < 1e-15 and abs(o.tau_in - 1e-12) < 1e-27 and o.refine == 4
 
 

@@ -254,3 +254,83 @@ def test_full_batch_sampled(gpu_lib, prec):
                 assert err < (1e-11 if prec == 0 else 1e-4), (i, l, lays[i], err)
     finally:
         W.dd_batch_destroy(b)
+
+
+def _oracle_dd(s, f, tol):
+    """The oracle DD of a problem dict (wavespeed and source sampled at the
+    oracle's own node coordinates by the given callables)."""
+    mesh = sem.Rect(s["nx"], s["ny"], s["P"], s["x0"], s["x1"], s["y0"], s["y1"])
+    X, Y = sem.node_coords(mesh)
+    dec = dd.Decomposition(mesh, dd.Partition(s["sx"], s["sy"]), s["cfun"](X, Y), s["omega"])
+    us, info = dd.solve_dd(dec, f(X, Y), tol=tol)
+    # plain GMRES from G = 0: one pass (none for a single subdomain, which
+    # has no interface unknowns)
+    assert info["passes"] == (1 if s["sx"] * s["sy"] > 1 else 0)
+    return dec.glue(us), info
+
+
+def test_engine_mix_matches_oracle_fp64(gpu_lib):
+    """Served FP64 results of a mixed stream (five shapes, P = 1..4, one of
+    them STREAM-sized, two submitted twice) against the oracle DD at the
+    same outer tolerance: 1e-10 and the same outer iteration count."""
+    W = gpu_lib
+    specs = [_spec(W, i) for i in range(len(SPECS))]
+    order = [4, 0, 1, 2, 3, 1, 0]
+    mix, info = _engine_run(W, specs, order, tau_in=1e-12, max_active=4)
+    assert info["done"] == len(order)
+    refs = {}
+    for (u, st, _, rc), k in zip(mix, order):
+        if k not in refs:
+            s = dict(specs[k], cfun=_c)
+            refs[k] = _oracle_dd(s, lambda X, Y, k=k: _f(X, Y, k), 1e-8)
+        u_ref, info_ref = refs[k]
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        print(f"served problem {k}: iters {st['outer_iters']} oracle {info_ref['iters']} "
+              f"err {err:.2e}", flush=True)
+        assert rc == W.DD_OK
+        assert st["outer_iters"] == info_ref["iters"], k
+        assert err < 1e-10, k
+
+
+def test_engine_c5_requests_alone_and_mixed_match_oracle(gpu_lib):
+    """Twenty requests drawn (seeded) from the serving stream among those of
+    at most 50,000 global nodes, FP32 sweeps with FP64 refinement, served
+    together and each alone: every result within 1e-6 of the FP64 oracle DD
+    at the same outer tolerance (1e-8 here, so that the bar is tighter than
+    the FP32 sweep accuracy), and the mixed result equal to the alone result
+    to the same bar (bitwise where both runs chose the same layout)."""
+    import workloads
+    W = gpu_lib
+    cand = [wl for wl in workloads.c5(n_requests=2000)
+            if (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1) <= 50000]
+    rng = np.random.default_rng(55)
+    pick = [cand[i] for i in sorted(rng.choice(len(cand), 20, replace=False))]
+    specs = [W.workload_spec(wl) for wl in pick]
+    tol = 1e-8
+    opt = dict(precision=W.DD_FP32, tau_in=1e-5, max_wh=1000)
+    e = W.dd_engine_create(8 << 30, 8, W.dd_default_options(**opt))
+    try:
+        ids = [W.dd_engine_submit(e, s, s["f"], tol, 3000) for s in specs]
+        mix = [W.dd_engine_wait(e, rid, s["c"].size) for rid, s in zip(ids, specs)]
+        info = W.dd_engine_get_info(e)
+    finally:
+        W.dd_engine_destroy(e)
+    print(f"c5 sample: {len(specs)} requests, nodes {[s['c'].size for s in specs]}, "
+          f"peak running {info['peak_running']}", flush=True)
+    for k, (s, wl) in enumerate(zip(specs, pick)):
+        e = W.dd_engine_create(8 << 30, 1, W.dd_default_options(**opt))
+        try:
+            rid = W.dd_engine_submit(e, s, s["f"], tol, 3000)
+            alone = W.dd_engine_wait(e, rid, s["c"].size)
+        finally:
+            W.dd_engine_destroy(e)
+        u_ref, _ = _oracle_dd(dict(s, cfun=wl.c), wl.f, tol)
+        u_mix, u_alone = mix[k][0], alone[0]
+        e_mix = np.linalg.norm(u_mix - u_ref) / np.linalg.norm(u_ref)
+        e_alone = np.linalg.norm(u_alone - u_ref) / np.linalg.norm(u_ref)
+        d = np.linalg.norm(u_mix - u_alone) / np.linalg.norm(u_alone)
+        print(f"request {wl.name}: n={wl.nx} P={wl.P} {wl.sx}x{wl.sy} subdomains, "
+              f"omega={wl.omega:.1f}: mix vs oracle {e_mix:.2e}, alone vs oracle {e_alone:.2e}, "
+              f"mix vs alone {d:.2e}", flush=True)
+        assert mix[k][3] == W.DD_OK and alone[3] == W.DD_OK
+        assert e_mix < 1e-6 and e_alone < 1e-6 and d < 1e-6, k

@@ -45,6 +45,7 @@ def test_converged_dd_equals_global_lu(part):
     err = np.linalg.norm(np.concatenate(us) - np.concatenate(ref)) / np.linalg.norm(np.concatenate(ref))
     assert err < 1e-10, (err, info["iters"])
     assert info["true_rel"] < 1e-10
+    assert info["passes"] == 1   # plain GMRES from G = 0
 
 
 def test_plane_wave_through_dd():
@@ -135,3 +136,65 @@ def test_waveholtz_inner_dd_matches_exact_dd():
     a, b = np.concatenate(us_wh), np.concatenate(us_ex)
     assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-9
     assert info_ex["iters"] == info_wh["iters"]
+
+
+@pytest.mark.parametrize("reduction", [1e-2, 1e-3])
+def test_refinement_passes_reach_global_lu(reduction):
+    """The refinement loop of the outer iteration (Krylov acceleration of
+    the interface iteration, Sec. III): passes limited to a fixed reduction
+    must chain through the true residual r = h - (I - T) G and the rescaled
+    tolerance to the global discrete solution.  A sign or scaling slip in
+    either stalls the passes or converges elsewhere."""
+    m, _, om, f = _c1()
+    X, Y = sem.node_coords(m)
+    c = 1.0 + 0.3 * np.sin(4 * X + 1) * np.cos(3 * Y)
+    dec = dd.Decomposition(m, dd.Partition(2, 2), c, om)
+    us, info = dd.solve_dd(dec, f, tol=1e-12, refine=12, reduction=reduction)
+    u = sem.solve(m, c, om, f)
+    ref = np.concatenate(dec.restrict(u))
+    err = np.linalg.norm(np.concatenate(us) - ref) / np.linalg.norm(ref)
+    # each pass buys at least the fixed reduction, and not many times more
+    need = int(np.ceil(np.log(1e-12) / np.log(reduction)))
+    assert need <= info["passes"] <= need + 2, info["passes"]
+    assert info["true_rel"] <= 1e-12
+    assert err < 1e-10, err
+    # the history is stated relative to ||h|| across passes; the last pass
+    # asks for exactly what is left (tol ||h|| / ||r||), so it stops at the
+    # first iterate below tol: an over- or under-scaled request would stop
+    # later or earlier
+    assert info["hist"][-1] <= 1e-12 < info["hist"][-2]
+
+
+def test_refinement_first_pass_is_plain_gmres():
+    """With no reduction limit the loop is one GMRES pass from G = 0: the
+    same iterates and iteration count as calling GMRES directly."""
+    m, c, om, f = _c1()
+    dec = dd.Decomposition(m, dd.Partition(2, 2), c, om)
+    us, info = dd.solve_dd(dec, f, tol=1e-10)
+    h, _ = dec.sweep(dec.embed_trace(None), f, 1.0)
+    G, its, _, _ = dd.gmres(lambda v: v - dec.sweep(v, f, 0.0)[0], h, 1e-10)
+    assert info["passes"] == 1 and info["iters"] == its
+    assert np.array_equal(info["G"], np.where(dec.interface_mask(), G, 0.0))
+
+
+def test_pool_sweep_equals_serial_sweep():
+    """The process-pool sweep assembles each output slot from the one
+    subdomain that writes it: bit for bit the serial sweep, and the same
+    outer solve."""
+    from oracle import pool
+    m, _, om, f = _c1()
+    X, Y = sem.node_coords(m)
+    c = 1.0 + 0.3 * np.sin(4 * X + 1) * np.cos(3 * Y)
+    part = dd.Partition(4, 2)
+    dec = dd.Decomposition(m, part, c, om)
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(dec.n_if) + 1j * rng.standard_normal(dec.n_if)
+    with pool.ParallelDecomposition(m, part, c, om, workers=3) as pdec:
+        a, ua = pdec.sweep(g, f, 1.0)
+        b, ub = dec.sweep(g, f, 1.0)
+        assert np.array_equal(a, b)
+        assert all(np.array_equal(x, y) for x, y in zip(ua, ub))
+        us1, i1 = dd.solve_dd(pdec, f, tol=1e-10)
+        us2, i2 = dd.solve_dd(dec, f, tol=1e-10)
+    assert i1["iters"] == i2["iters"]
+    assert all(np.array_equal(x, y) for x, y in zip(us1, us2))
