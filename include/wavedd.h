@@ -210,6 +210,20 @@ int dd_apply_stiffness(dd_handle* h, const double* p, double* q);
 int dd_residual(dd_handle* h, const double* u_re, const double* u_im, const double* f_re,
                 const double* f_im, const double* g_re, const double* g_im, double* rel);
 
+/* Same residual for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid allocation): device
+ * arrays (u_re, u_im, f_re, f_im: N each; g_re, g_im: the boundary trace,
+ * 2*Ny + 2*Nx each; all but u_re may be NULL), the result ||b - S u|| / ||b||
+ * written to d_rel[0] (device) in stream order (NULL stream = the handle's
+ * stream; no synchronisation).  Nothing is allocated: the row partials of
+ * the reduction live in a library array of 16384 entries per GPU, so meshes
+ * of more than 16384 grid rows (Ny = ny*P + 1) are rejected with DD_EINVAL.
+ * Calls on one GPU share that array: two calls in flight at once (different
+ * streams, or different handles on the same GPU) race. */
+int dd_residual_device_noalloc(dd_handle* h, void* stream, const double* d_u_re,
+                               const double* d_u_im, const double* d_f_re, const double* d_f_im,
+                               const double* d_g_re, const double* d_g_im, double* d_rel);
+
 /* Whole-domain operator y = S x in FP64 on device arrays (x, y: N complex,
  * interleaved re/im): the normaliser of the paper's DD-time/operator-time
  * ratio (Sec. VII-A). */

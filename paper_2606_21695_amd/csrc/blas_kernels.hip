@@ -5,7 +5,7 @@
 //
 // Reductions are deterministic: fixed-size block partials, then one block
 // sums the partials in a fixed order.
-#include "wavedd_internal.h"
+#include "operator_device.h"
 
 namespace wdd {
 
@@ -23,19 +23,7 @@ __device__ __forceinline__ double2 cdotc(double2 a, double2 b) {
 }
 
 __device__ __forceinline__ double2 block_sum(double2 v, double2* sh) {
-    for (int off = 32; off > 0; off >>= 1) {
-        v.x += __shfl_xor(v.x, off, 64);
-        v.y += __shfl_xor(v.y, off, 64);
-    }
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double2 s = make_double2(0.0, 0.0);
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = cadd(s, sh[i]);
-    }
-    __syncthreads();
-    return s;
+    return block_sum_d2(v, sh);
 }
 
 // partial[blk * k + i] = sum over this block's chunk of conj(V_i) w
@@ -182,45 +170,6 @@ __global__ void glue_kernel(const double2* usub, int Nx, int Ny, int P, int mx, 
 // degree is a template parameter so the element windows unroll and the
 // reference matrix entries stay in scalar registers.
 
-// Row a of the reference element matrix, selected with compile-time
-// indices (a is the node's offset inside its element).
-template <int P>
-__device__ __forceinline__ double kref(const double (*K)[kMaxP + 1], int a, int q) {
-    double v = K[0][q];
-#pragma unroll
-    for (int r = 1; r <= P; ++r) v = (a == r) ? K[r][q] : v;
-    return v;
-}
-
-// Assembled 1D stiffness row at node k of a line of n_el elements, applied
-// to x along the line (nodes base + m * step).
-template <int P>
-__device__ __forceinline__ double2 line1d(const double2* x, int64_t base, int64_t step, int k,
-                                          int n_el, const double (*K)[kMaxP + 1]) {
-    const int e = k / P, a = k - e * P;
-    double2 s = make_double2(0.0, 0.0);
-    // element e (row a), present unless k is the last node of the line
-    if (e < n_el) {
-#pragma unroll
-        for (int q = 0; q <= P; ++q) {
-            const double kv = kref<P>(K, a, q);
-            const double2 v = x[base + (int64_t)(e * P + q) * step];
-            s.x += kv * v.x;
-            s.y += kv * v.y;
-        }
-    }
-    // element e - 1 (row P) at a vertex
-    if (a == 0 && e > 0) {
-#pragma unroll
-        for (int q = 0; q <= P; ++q) {
-            const double2 v = x[base + (int64_t)((e - 1) * P + q) * step];
-            s.x += K[P][q] * v.x;
-            s.y += K[P][q] * v.y;
-        }
-    }
-    return s;
-}
-
 // Node (i, j) of the block's grid row; false past the row's end.
 __device__ __forceinline__ bool grid_node(const OperatorArgs& A, int& i, int& j) {
     const int bpr = (A.Nx + kBT - 1) / kBT;
@@ -234,15 +183,7 @@ __global__ void __launch_bounds__(kBT) operator_kernel(const OperatorArgs A, con
                                                        double2* y) {
     int i, j;
     if (!grid_node(A, i, j)) return;
-    const int64_t g = (int64_t)j * A.Nx + i;
-    const double2 X = line1d<P>(x, (int64_t)j * A.Nx, 1, i, A.nx, A.K1);
-    const double2 Y = line1d<P>(x, i, A.Nx, j, A.ny, A.K1);
-    const double cx = A.sx_ref * A.wy[j], cy = A.sy_ref * A.wx[i];
-    const double2 v = x[g];
-    const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
-    // (A - i omega H - omega^2 M) v
-    y[g] = make_double2(cx * X.x + cy * Y.x - m * v.x + h * v.y,
-                        cx * X.y + cy * Y.y - m * v.y - h * v.x);
+    y[(int64_t)j * A.Nx + i] = apply_node<P>(A, Interleaved{x}, i, j);
 }
 
 // Per node: r = b - S u with b = (Wx Wy) f + boundary trace terms; writes
@@ -254,27 +195,8 @@ __global__ void __launch_bounds__(kBT) residual_kernel(const OperatorArgs A, con
                                                        double2* out) {
     int i, j;
     if (!grid_node(A, i, j)) return;
-    const int Nx = A.Nx, Ny = A.Ny;
-    const int64_t g = (int64_t)j * Nx + i;
-    double br = 0.0, bi = 0.0;
-    const double area = A.wx[i] * A.wy[j];
-    if (f_re) br = area * f_re[g];
-    if (f_im) bi = area * f_im[g];
-    // boundary trace (left, right, bottom, top)
-    const int64_t tl = j, tr = Ny + j, tb = 2 * (int64_t)Ny + i, tt = 2 * (int64_t)Ny + Nx + i;
-    if (i == 0) { if (g_re) br += A.wy[j] * g_re[tl]; if (g_im) bi += A.wy[j] * g_im[tl]; }
-    if (i == Nx - 1) { if (g_re) br += A.wy[j] * g_re[tr]; if (g_im) bi += A.wy[j] * g_im[tr]; }
-    if (j == 0) { if (g_re) br += A.wx[i] * g_re[tb]; if (g_im) bi += A.wx[i] * g_im[tb]; }
-    if (j == Ny - 1) { if (g_re) br += A.wx[i] * g_re[tt]; if (g_im) bi += A.wx[i] * g_im[tt]; }
-    const double2 X = line1d<P>(u, (int64_t)j * Nx, 1, i, A.nx, A.K1);
-    const double2 Y = line1d<P>(u, i, Nx, j, A.ny, A.K1);
-    const double cx = A.sx_ref * A.wy[j], cy = A.sy_ref * A.wx[i];
-    const double2 v = u[g];
-    const double m = A.omega * A.omega * A.M[g], h = A.omega * A.H[g];
-    const double sr = cx * X.x + cy * Y.x - m * v.x + h * v.y;
-    const double si = cx * X.y + cy * Y.y - m * v.y - h * v.x;
-    const double rr = br - sr, ri = bi - si;
-    out[g] = make_double2(rr * rr + ri * ri, br * br + bi * bi);
+    out[(int64_t)j * A.Nx + i] =
+        residual_node<P>(A, Interleaved{u}, f_re, f_im, g_re, g_im, i, j);
 }
 
 // partial[blk] = sum of v over this block's chunk (both components)

@@ -1116,6 +1116,15 @@ int ensure_staging(dd_handle* h) {
     return DD_OK;
 }
 
+// Device address of the no-allocation scratch array on the handle's device
+// (looked up once per device, with that device current).
+int noalloc_init(const dd_handle* h) {
+    HIPCHK(hipSetDevice(h->dev));
+    double2* p = nullptr;
+    HIPCHK(wdd::noalloc_scratch(h->dev, &p));
+    return DD_OK;
+}
+
 wdd::OperatorArgs op_args(const dd_handle* h) {
     wdd::OperatorArgs a{};
     a.Nx = h->Nx;
@@ -1761,6 +1770,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     if (rc == DD_OK) rc = upload(h, ha);
     if (rc == DD_OK && h->opt.layout == DD_LAYOUT_AUTO && h->layout != DD_LAYOUT_STREAM)
         rc = autotune_layout(h);
+    if (rc == DD_OK) rc = noalloc_init(h);
     if (rc != DD_OK) {
         dd_destroy(h);
         return rc;
@@ -2029,6 +2039,25 @@ int dd_apply_operator_device(dd_handle* h, void* stream, const double* d_x, doub
     HIPCHK(hipSetDevice(h->dev));
     hipStream_t s = stream ? (hipStream_t)stream : h->stream;
     HIPCHK(wdd::launch_operator(op_args(h), (const double2*)d_x, (double2*)d_y, s));
+    return DD_OK;
+}
+
+int dd_residual_device_noalloc(dd_handle* h, void* stream, const double* d_u_re,
+                               const double* d_u_im, const double* d_f_re, const double* d_f_im,
+                               const double* d_g_re, const double* d_g_im, double* d_rel) {
+    CHK(validate_handle(h));
+    if (!d_u_re || !d_rel) return fail(DD_EINVAL, "null array");
+    if (h->Ny > wdd::kNoAllocMaxRows)
+        return fail(DD_EINVAL,
+                    "dd_residual_device_noalloc: the mesh has %d grid rows; at most %d fit "
+                    "its scratch array (use dd_residual)",
+                    (int)h->Ny, wdd::kNoAllocMaxRows);
+    HIPCHK(hipSetDevice(h->dev));
+    double2* part = nullptr;
+    HIPCHK(wdd::noalloc_scratch(h->dev, &part));
+    hipStream_t s = stream ? (hipStream_t)stream : h->stream;
+    HIPCHK(wdd::launch_residual_noalloc(op_args(h), d_u_re, d_u_im, d_f_re, d_f_im, d_g_re,
+                                        d_g_im, part, d_rel, s));
     return DD_OK;
 }
 

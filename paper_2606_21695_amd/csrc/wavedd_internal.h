@@ -147,6 +147,18 @@ struct OperatorArgs {
     double K1[kMaxP + 1][kMaxP + 1];
 };
 hipError_t launch_operator(const OperatorArgs& a, const double2* x, double2* y, hipStream_t s);
+
+// No-allocation residual (noalloc.hip): at most this many grid rows.
+constexpr int kNoAllocMaxRows = 16384;
+// Device address of the no-allocation scratch array on device dev, which
+// must be the current device; looked up once per device, then cached.
+hipError_t noalloc_scratch(int dev, double2** ptr);
+// out[0] = ||b - S u|| / ||b|| for device planes u, f, g (f, g, u_im may be
+// null); part: the scratch array (Ny row partials).  No allocation.
+hipError_t launch_residual_noalloc(const OperatorArgs& a, const double* u_re, const double* u_im,
+                                   const double* f_re, const double* f_im, const double* g_re,
+                                   const double* g_im, double2* part, double* out,
+                                   hipStream_t s);
 // work[g] = (|b - S u|^2, |b|^2) per global node (f, g may be null).
 hipError_t launch_residual(const OperatorArgs& a, const double2* u, const double* f_re,
                            const double* f_im, const double* g_re, const double* g_im,

@@ -24,7 +24,8 @@ DD_OUTER_GMRES, DD_OUTER_FIXED = 0, 1
 EXPORTS = [
     "dd_default_options", "dd_setup", "dd_destroy", "dd_last_error", "dd_sizes",
     "dd_node_coords", "dd_time_steps", "dd_solve", "dd_solve_device", "dd_sweep",
-    "dd_apply_stiffness", "dd_residual", "dd_apply_operator_device", "dd_get_state",
+    "dd_apply_stiffness", "dd_residual", "dd_residual_device_noalloc",
+    "dd_apply_operator_device", "dd_get_state",
     "dd_set_state", "dd_time_sweep", "dd_layout", "dd_mesh_coords",
     "dd_batch_setup", "dd_batch_destroy", "dd_batch_handle", "dd_batch_solve",
     "dd_batch_time_sweep", "dd_batch_launches", "dd_batch_wait_progress",
@@ -149,6 +150,7 @@ def load():
         "dd_sweep": ([P, D, D, D, D, C.c_double, D, D, D, D, C.POINTER(C.c_int)], C.c_int),
         "dd_apply_stiffness": ([P, D, D], C.c_int),
         "dd_residual": ([P, D, D, D, D, D, D, D], C.c_int),
+        "dd_residual_device_noalloc": ([P, P, P, P, P, P, P, P, P], C.c_int),
         "dd_apply_operator_device": ([P, P, P, P], C.c_int),
         "dd_get_state": ([P, D], C.c_int),
         "dd_set_state": ([P, D], C.c_int),
@@ -372,6 +374,22 @@ def dd_residual(h, u, f=None, g=None):
     _check(load().dd_residual(h, _dp(_f64(u.real)), _dp(_f64(u.imag)), _dp(f_re), _dp(f_im),
                               _dp(g_re), _dp(g_im), C.byref(rel)))
     return rel.value
+
+
+def dd_residual_device_noalloc(h, u_re, u_im=None, f_re=None, f_im=None, g_re=None, g_im=None,
+                               out=None, stream=None):
+    """||b - S u|| / ||b|| on torch float64 device tensors without device
+    allocation by the library; written to out[0] (a float64 device tensor,
+    allocated here when not given) in stream order."""
+    import torch
+    def ptr(t):
+        return None if t is None else C.c_void_p(t.data_ptr())
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=u_re.device)
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(load().dd_residual_device_noalloc(h, sp, ptr(u_re), ptr(u_im), ptr(f_re), ptr(f_im),
+                                             ptr(g_re), ptr(g_im), ptr(out)))
+    return out
 
 
 def dd_apply_operator_device(h, x, y, stream=None):
