@@ -136,6 +136,7 @@ __device__ void sweep3_item(const Sweep3Args<Real>& A, const Sub3& d, int item, 
     const int nt = d.nt;
     int it = 0;
     Real p = Real(0), pd = Real(0), vr = Real(0), vi = Real(0);
+    WhStall stall;
     for (int m = 0; m < A.max_wh; ++m) {
         // p = Re u, pdot^{1/2} = Re{-i omega u e^{-i pi/N_t}}, v = kappa_0 p + (i/omega) kappa_{1/2} pdot
         p = pd = Real(0);
@@ -191,7 +192,7 @@ __device__ void sweep3_item(const Sweep3Args<Real>& A, const Sub3& d, int item, 
         block_sum2_3(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (A.tau > 0.0 && dsum <= A.tau * A.tau * nsum) break;
+        if (wh_stop<Real>(A.tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
     __syncthreads();

@@ -537,6 +537,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
     // warm start: the first WaveHoltz iteration starts from the current u
     const bool warm = A.warm != 0 || (d.flags & 1) != 0;
+    WhStall stall;
     for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
         // p, pdot from u: read at the first iteration (warm start), after
@@ -718,7 +719,7 @@ __device__ void sweep_patch_item(const SweepArgs<Real>& A, const SubDesc& d, int
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;  // non-finite iterate: stop, reported by the host
-        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
+        if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -989,6 +990,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
     // warm start: the first WaveHoltz iteration starts from the current u
     const bool warm = A.warm != 0 || (d.flags & 1) != 0;
+    WhStall stall;
     for (int m = 0; m < max_wh; ++m) {
         const Real k0 = TAB[2], kh0 = TAB[3];
 #pragma unroll
@@ -1148,7 +1150,7 @@ __device__ void sweep_patch1_item(const SweepArgs<Real>& A, const SubDesc& d, in
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
+        if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -1318,6 +1320,7 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
     // warm start: the first WaveHoltz iteration starts from the current u
     const bool warm = A.warm != 0 || (d.flags & 1) != 0;
+    WhStall stall;
     for (int m = 0; m < max_wh; ++m) {
         if (C.has) slot_init(s, A, d, m > 0 || warm, TAB[2], TAB[3]);
         for (int nu = 1; nu < nt; ++nu) {
@@ -1340,7 +1343,7 @@ __device__ void sweep_node_item(const SweepArgs<Real>& A, const SubDesc& d, int 
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
+        if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
     __syncthreads();
@@ -1439,6 +1442,7 @@ template <typename Real, int P>
 struct StreamGeom {
     int lane, i, ic, pcol, j0, j1;
     bool active, colv, own;
+    bool side_col;   // every node of this lane's column reads its side record
     Real wx[2 * P + 1];
 
     __device__ void setup(int nxl, int nyl, const Real* WT) {
@@ -1470,37 +1474,64 @@ struct StreamGeom {
 template <typename Real>
 constexpr int stream_ahead() { return sizeof(Real) == 8 ? 2 : 4; }
 
-// STREAM workspace per node: the state quad {pd, vr, vi, alpha} in one
-// plane and the coefficient quad {betaX, betaY, beta Re b, beta Im b} in a
-// second (so the cache lines a step writes hold state only).  A step reads
-// both quads and writes the state quad.
+// STREAM workspace per node, in three planes: the state triple {pd, vr, vi}
+// (read and written every step), the coefficient pair {betaX, betaY} (read
+// every step) and the side triple {alpha, beta Re b, beta Im b}.  The side
+// triple differs from {1, 0, 0} only on the subdomain's sides (H != 0
+// there; the interface data enter b there) and, in sweeps with a source,
+// wherever the source is; every other node reads one shared record
+// {1, 0, 0} that the store keeps after the last side triple, so a step
+// moves 10 words per node: p in and out, the state triple in and out, the
+// pair in.
 template <typename Real>
 struct alignas(4 * sizeof(Real)) Quad {
     Real a, b, c, d;
 };
+template <typename Real>
+struct Triple {
+    Real a, b, c;
+};
+template <typename Real>
+struct alignas(2 * sizeof(Real)) Pair {
+    Real a, b;
+};
+
+// Planes of the STREAM workspace of a launch (see above).
+template <typename Real>
+struct StreamPlanes {
+    Real* st;          // state triples, 3 per node
+    const Real* cf;    // coefficient pairs, 2 per node
+    const Real* sd;    // side triples, 3 per node
+    const Real* sd1;   // the shared record {1, 0, 0}
+};
 
 // One row's loads of one lane: p entering the Y window (row j + P) and the
-// node record at row j.  The loads are unconditional (addresses clamped to
-// the segment and the grid, values of lanes or rows outside selected away),
-// so no branch separates a load from its use and the wait counts let the
-// rows ahead stay in flight.
+// node records at row j.  The loads are unconditional (addresses clamped to
+// the segment and the grid, values of lanes or rows outside selected away,
+// nodes off the sides pointed at the shared record), so no branch separates
+// a load from its use and the wait counts let the rows ahead stay in
+// flight.
 template <typename Real>
 struct StreamRow {
     Real pn;
-    Quad<Real> st, cf;
+    Triple<Real> st;
+    Pair<Real> cf;
+    Triple<Real> sd;
 };
 
 template <typename Real, int P>
 __device__ __forceinline__ void stream_fetch(StreamRow<Real>& r, const StreamGeom<Real, P>& G,
-                                             const Real* cur, int stride, int j, int nxl,
-                                             const Real* NSt, const Real* NCf) {
+                                             const Real* cur, int stride, int j, int nxl, int nyl,
+                                             const StreamPlanes<Real>& N) {
     const bool inrow = j < G.j1;
     const int jc = inrow ? j : G.j1 - 1;
     const Real pn = cur[(jc + P + kMaxP) * stride + G.pcol];
     r.pn = (G.colv && inrow) ? pn : Real(0);
     const size_t n = (size_t)(jc * nxl + G.ic);
-    r.st = *reinterpret_cast<const Quad<Real>*>(NSt + 4 * n);
-    r.cf = *reinterpret_cast<const Quad<Real>*>(NCf + 4 * n);
+    r.st = *reinterpret_cast<const Triple<Real>*>(N.st + 3 * n);
+    r.cf = *reinterpret_cast<const Pair<Real>*>(N.cf + 2 * n);
+    const bool side = G.side_col || jc == 0 || jc == nyl - 1;
+    r.sd = *reinterpret_cast<const Triple<Real>*>(side ? N.sd + 3 * n : N.sd1);
 }
 
 // One step of the STREAM layout for the column segment of this lane: walk
@@ -1511,7 +1542,8 @@ __device__ __forceinline__ void stream_fetch(StreamRow<Real>& r, const StreamGeo
 // writes u = (2/N_t) v and accumulates the fixed-point residual instead.
 template <typename Real, int P, bool LAST>
 __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const Real* cur, Real* nxt,
-                                            int stride, int nxl, int nyl, Real* NSt, const Real* NCf,
+                                            int stride, int nxl, int nyl,
+                                            const StreamPlanes<Real>& N,
                                             const Real* WT,
                                             const Quad<Real> tb, Real sig, const SweepArgs<Real>& A,
                                             const SubDesc& d, bool has_old, double& dsum,
@@ -1527,13 +1559,14 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
     }
     StreamRow<Real> R[kAhead];
 #pragma unroll
-    for (int q = 0; q < kAhead; ++q) stream_fetch(R[q], G, cur, stride, G.j0 + q, nxl, NSt, NCf);
+    for (int q = 0; q < kAhead; ++q)
+        stream_fetch(R[q], G, cur, stride, G.j0 + q, nxl, nyl, N);
     for (int jb = G.j0; jb < G.j1; jb += kAhead) {
 #pragma unroll
         for (int q = 0; q < kAhead; ++q) {
             const int j = jb + q;
             const StreamRow<Real> r = R[q];
-            stream_fetch(R[q], G, cur, stride, j + kAhead, nxl, NSt, NCf);
+            stream_fetch(R[q], G, cur, stride, j + kAhead, nxl, nyl, N);
 #pragma unroll
             for (int k = 0; k < 2 * P; ++k) win[k] = win[k + 1];
             win[2 * P] = r.pn;
@@ -1546,19 +1579,19 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
                 X = fma(G.wx[k], nb, X);
                 Y = fma(wy[k], win[k], Y);
             }
-            Real t = r.cf.c * tb.a;
-            t = fma(r.cf.d, tb.b, t);
+            Real t = r.sd.b * tb.a;
+            t = fma(r.sd.c, tb.b, t);
             t = fma(-r.cf.a, X, t);
             t = fma(-r.cf.b, Y, t);
-            const Real pd = fma(r.st.d, r.st.a, t);
+            const Real pd = fma(r.sd.a, r.st.a, t);
             const Real vr = fma(tb.c, p, r.st.b);
             const Real vi = fma(tb.d, pd, r.st.c);
             const bool put = G.own && j < G.j1;
             const int n = j * nxl + G.i;
             if (!LAST) {
                 if (put) {
-                    *reinterpret_cast<Quad<Real>*>(NSt + 4 * (size_t)n) =
-                        Quad<Real>{pd, vr, vi, r.st.d};
+                    *reinterpret_cast<Triple<Real>*>(N.st + 3 * (size_t)n) =
+                        Triple<Real>{pd, vr, vi};
                     nxt[(j + kMaxP) * stride + G.pcol] = fma(sig, pd, p);
                 }
             } else if (put) {
@@ -1592,18 +1625,24 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const Real* TAB = lds + kStreamTab;
     Real* p0 = A.ws_p + d.ws_off;
     Real* p1 = p0 + stream_pad_nodes(nxl, nyl);
-    Real* NSt = A.ws_s + 4 * (size_t)d.node_off;
-    Real* NCf = A.ws_s + 4 * ((size_t)A.ws_stride + d.node_off);
-    const Real* AL = A.coef.alpha + d.node_off;
-    // beta * b (eq. (4) right-hand side with the interface data)
+    const size_t cap = (size_t)A.ws_stride;
+    Real* NSt = A.ws_s + 3 * (size_t)d.node_off;
+    Real* NCf = A.ws_s + 3 * cap + 2 * (size_t)d.node_off;
+    Real* NSd = A.ws_s + 5 * cap + 3 * (size_t)d.node_off;
+    const StreamPlanes<Real> N{NSt, NCf, NSd, A.ws_s + kStreamRecord * cap};
+    // interior nodes carry forcing only in sweeps with a source
+    const bool all_sides = A.Fre != nullptr && A.src != 0.0;
+    // the coefficient pair, and alpha with beta * b (eq. (4) right-hand side
+    // with the interface data) in the side triple
     {
         int il = tid % nxl, jl = tid / nxl;
         for (int n = tid; n < nloc; n += bd) {
             const double be = (double)A.coef.beta[d.node_off + n];
             const double2 b = assemble_b(A, d, il, jl);
-            *reinterpret_cast<Quad<Real>*>(NCf + 4 * (size_t)n) =
-                Quad<Real>{A.coef.betaX[d.node_off + n], A.coef.betaY[d.node_off + n],
-                           (Real)(be * b.x), (Real)(be * b.y)};
+            *reinterpret_cast<Pair<Real>*>(NCf + 2 * (size_t)n) =
+                Pair<Real>{A.coef.betaX[d.node_off + n], A.coef.betaY[d.node_off + n]};
+            *reinterpret_cast<Triple<Real>*>(NSd + 3 * (size_t)n) =
+                Triple<Real>{A.coef.alpha[d.node_off + n], (Real)(be * b.x), (Real)(be * b.y)};
             il += di;
             jl += dj;
             if (il >= nxl) { il -= nxl; ++jl; }
@@ -1612,6 +1651,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     __syncthreads();
     StreamGeom<Real, P> G;
     G.setup(nxl, nyl, WT);
+    G.side_col = all_sides || G.ic == 0 || G.ic == nxl - 1;
     const Real sig = (Real)d.sigma;
     const int nt = d.nt;
     int it = 0;
@@ -1619,6 +1659,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
     const double tau = d.max_wh > 0 ? d.tau : A.tau;
     // warm start: the first WaveHoltz iteration starts from the current u
     const bool warm = A.warm != 0 || (d.flags & 1) != 0;
+    WhStall stall;
     for (int m = 0; m < max_wh; ++m) {
         // u -> (p^1, pdot^{1/2}, v)
         {
@@ -1631,8 +1672,8 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
                     p = (Real)u.x;
                     pd = (Real)(u.y * d.pd0c - u.x * d.pd0s);
                 }
-                *reinterpret_cast<Quad<Real>*>(NSt + 4 * (size_t)n) =
-                    Quad<Real>{pd, k0 * p, kh0 * pd, AL[n]};
+                *reinterpret_cast<Triple<Real>*>(NSt + 3 * (size_t)n) =
+                    Triple<Real>{pd, k0 * p, kh0 * pd};
                 p1[(jl + kMaxP) * stride + il + kMaxP] = fma(sig, pd, p);
                 il += di;
                 jl += dj;
@@ -1647,16 +1688,16 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             if (!G.active) continue;
             const Quad<Real> tb{TAB[4 * nu + 0], TAB[4 * nu + 1], TAB[4 * nu + 2], TAB[4 * nu + 3]};
             if (nu < nt - 1)
-                stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
-                                            A, d, m > 0 || warm, dsum, nsum);
+                stream_rows<Real, P, false>(G, cur, nxt, stride, nxl, nyl, N, WT, tb, sig, A, d,
+                                            m > 0 || warm, dsum, nsum);
             else
-                stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, NSt, NCf, WT, tb, sig,
-                                           A, d, m > 0 || warm, dsum, nsum);
+                stream_rows<Real, P, true>(G, cur, nxt, stride, nxl, nyl, N, WT, tb, sig, A, d,
+                                           m > 0 || warm, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
         it = m + 1;
         if (!(dsum == dsum)) break;
-        if (tau > 0.0 && dsum <= tau * tau * nsum) break;
+        if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
     __syncthreads();

@@ -308,9 +308,15 @@ struct Store {
     int* h_work_iters = nullptr;
     hipStream_t ss[Sched::kSlots] = {};   // launch slot streams (shared stores)
     hipEvent_t sev0[Sched::kSlots] = {}, sev1[Sched::kSlots] = {};
+    // the launch groups of one slot's round run concurrently on sub-streams:
+    // sevc (work list staged) starts them, gev (group done) joins them
+    static constexpr int kSub = 4;
+    hipStream_t gs[Sched::kSlots][kSub] = {};
+    hipEvent_t sevc[Sched::kSlots] = {}, gev[Sched::kSlots][kSub] = {};
+    int sub_streams = kSub;   // sub-streams used per round (1: all groups in order on ss)
     size_t bytes = 0;
     std::mutex mu;            // allocators, layout cache
-    std::map<std::tuple<int, int, int, int>, int> layout_cache;  // (mx, my, P, prec) -> layout
+    std::map<std::tuple<int, int, int, int>, std::pair<int, int>> layout_cache;  // (mx, my, P, prec) -> (layout, wg)
     Sched sched;
 };
 
@@ -449,10 +455,23 @@ size_t layout_lds(const dd_handle* h, int layout, int prec) {
     return wdd::patch1_lds_bytes(h->mx, h->my, h->P, layout_threads(h, layout), h->nt_max, rs);
 }
 
-void layout_config(dd_handle* h, int layout) {
+void layout_config(dd_handle* h, int layout, int wg = 0) {
     h->layout = layout;
-    h->wg = layout_threads(h, layout);
+    h->wg = wg > 0 ? wg : layout_threads(h, layout);
     for (int prec : {DD_FP64, DD_FP32}) h->lds[prec_index(prec)] = layout_lds(h, layout, prec);
+}
+
+// Workgroup sizes the STREAM layout can run with on this subdomain: every
+// column group of its step loop needs a wave, and the kernel is built for
+// at most 512 threads.
+std::vector<int> stream_wg_options(const dd_handle* h) {
+    const int ow = 64 - 2 * h->P, groups = (h->nxl + ow - 1) / ow;
+    std::vector<int> out;
+    for (int wg : {256, 512})
+        if (groups <= wg / 64 && wg <= ((std::min<int64_t>(512, h->nloc) + 63) / 64) * 64)
+            out.push_back(wg);
+    if (out.empty()) out.push_back(layout_threads(h, DD_LAYOUT_STREAM));
+    return out;
 }
 
 // Fits in one workgroup for every precision the handle carries (FP64
@@ -643,11 +662,38 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
         HIPCHK(hipMemcpyAsync(S->d_gin.p + q->h->if_base, q->g_in, sizeof(double2) * q->h->n_if,
                               hipMemcpyDeviceToDevice, s));
     const double(*K1)[wdd::kMaxP + 1][wdd::kMaxP + 1] = reqs[0]->h->K1all;
+    // Groups (one launch each) go to sub-streams by longest processing time
+    // first: the costliest group to the least-loaded sub-stream, so the
+    // groups of a round overlap on the device and short launches fill the
+    // CUs that a long launch's tail leaves idle.
+    std::vector<Group*> order;
+    for (auto& kv : groups)
+        if (!kv.second.items.empty()) order.push_back(&kv.second);
+    auto gcost = [](const Group* g) {
+        double c = 0.0;
+        for (const Item& it : g->items) c += it.cost;
+        return c;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](const Group* a, const Group* b) { return gcost(a) > gcost(b); });
+    const int nsub = std::max(1, std::min<int>(S->sub_streams, (int)order.size()));
+    double load[Store::kSub] = {};
+    bool used[Store::kSub] = {};
+    if (nsub > 1) HIPCHK(hipEventRecord(S->sevc[slot], s));
     int gi = 0;
-    for (auto& kv : groups) {
-        Group& g = kv.second;
-        if (g.items.empty()) continue;
+    for (Group* gp : order) {
+        Group& g = *gp;
         ++gi;
+        hipStream_t gstream = s;
+        if (nsub > 1) {
+            int k = 0;
+            for (int j = 1; j < nsub; ++j)
+                if (load[j] < load[k]) k = j;
+            load[k] += gcost(gp);
+            gstream = S->gs[slot][k];
+            if (!used[k]) HIPCHK(hipStreamWaitEvent(gstream, S->sevc[slot], 0));
+            used[k] = true;
+        }
         const bool wf = g.src != 0.0;
         hipError_t e;
         if (g.prec == DD_FP32) {
@@ -657,7 +703,7 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
             a.wh_iters = di + g.off;
             a.lds_bytes = g.lds;
             a.nt_max = g.nt_max;
-            e = launch_layout<float>(g.layout, a, g.P, g.wg, s);
+            e = launch_layout<float>(g.layout, a, g.P, g.wg, gstream);
         } else {
             auto a = store_args<double>(S, S->d_gin.p, S->d_gout.p, g.src, wf, 0.0, 1, K1);
             a.desc = dw + g.off;
@@ -665,9 +711,14 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
             a.wh_iters = di + g.off;
             a.lds_bytes = g.lds;
             a.nt_max = g.nt_max;
-            e = launch_layout<double>(g.layout, a, g.P, g.wg, s);
+            e = launch_layout<double>(g.layout, a, g.P, g.wg, gstream);
         }
         HIPCHK(e);
+    }
+    for (int k = 0; k < nsub && nsub > 1; ++k) {
+        if (!used[k]) continue;
+        HIPCHK(hipEventRecord(S->gev[slot][k], S->gs[slot][k]));
+        HIPCHK(hipStreamWaitEvent(s, S->gev[slot][k], 0));
     }
     HIPCHK(hipEventRecord(S->sev1[slot], s));
     for (const SweepReq* q : reqs)
@@ -1147,12 +1198,28 @@ wdd::OperatorArgs op_args(const dd_handle* h) {
 // Layout autotuner: time every layout that fits on this problem (two
 // fixed-count WaveHoltz iterations per subdomain, zero data: the kernels
 // have no data-dependent work) and keep the fastest.
+// Layout and workgroup size of a subdomain shape, by timing: three sweeps
+// of two WaveHoltz iterations each with every candidate that fits.  The
+// candidates are the on-chip layouts (one element patch per thread with two
+// or one barrier per step, one node per thread) at their natural
+// workgroup sizes and, for subdomains that only the STREAM layout holds,
+// STREAM at each workgroup size it can run with (256 or 512 threads: 64-2P
+// columns per wave, the rows of a column group split over the waves).
 int autotune_layout(dd_handle* h) {
-    int best = h->layout;
+    struct Cand {
+        int layout, wg;
+    };
+    std::vector<Cand> cands;
+    if (h->layout == DD_LAYOUT_STREAM) {
+        for (int wg : stream_wg_options(h)) cands.push_back({DD_LAYOUT_STREAM, wg});
+    } else {
+        for (int lay : {DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_NODE})
+            if (layout_fits(h, lay)) cands.push_back({lay, layout_threads(h, lay)});
+    }
+    Cand best{h->layout, h->wg};
     double best_ms = 1e300;
-    for (int lay : {DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_NODE}) {
-        if (!layout_fits(h, lay)) continue;
-        layout_config(h, lay);
+    for (const Cand& c : cands) {
+        layout_config(h, c.layout, c.wg);
         HIPCHK(hipMemsetAsync(h->d_g0.p, 0, sizeof(double2) * h->n_if, h->stream));
         CHK(run_sweep(h, h->d_g0.p, h->d_tmp.p, 0.0, false, false, h->opt.precision, 0.0, 2));
         reset_stats(h);
@@ -1161,10 +1228,10 @@ int autotune_layout(dd_handle* h) {
         const double ms = h->st.sweep_seconds;
         if (ms < best_ms) {
             best_ms = ms;
-            best = lay;
+            best = c;
         }
     }
-    layout_config(h, best);
+    layout_config(h, best.layout, best.wg);
     reset_stats(h);
     return DD_OK;
 }
@@ -1458,6 +1525,12 @@ void store_destroy(Store* S) {
     if (S->h_work_iters) (void)hipHostFree(S->h_work_iters);
     for (int i = 0; i < Sched::kSlots; ++i) {
         if (S->ss[i]) (void)hipStreamSynchronize(S->ss[i]);
+        for (int k = 0; k < Store::kSub; ++k) {
+            if (S->gs[i][k]) (void)hipStreamSynchronize(S->gs[i][k]);
+            if (S->gev[i][k]) (void)hipEventDestroy(S->gev[i][k]);
+            if (S->gs[i][k]) (void)hipStreamDestroy(S->gs[i][k]);
+        }
+        if (S->sevc[i]) (void)hipEventDestroy(S->sevc[i]);
         if (S->sev0[i]) (void)hipEventDestroy(S->sev0[i]);
         if (S->sev1[i]) (void)hipEventDestroy(S->sev1[i]);
         if (S->ss[i]) (void)hipStreamDestroy(S->ss[i]);
@@ -1519,13 +1592,23 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
     STCHK(S->d_u.alloc(cn));
     bytes += cit * (sizeof(wdd::SubDesc) + 4) + cw * 8 + ci * 20 + cn * 28;
     if (cwsp > 0) {
+        // STREAM workspace: kStreamRecord Reals per node, then the interior
+        // record {1, 0, 0} (and a zero pad) that nodes off the subdomain
+        // sides read
+        const int64_t nws = wdd::kStreamRecord * cn + wdd::kStreamExtra;
+        const double one64[wdd::kStreamExtra] = {1.0, 0.0, 0.0, 0.0};
+        const float one32[wdd::kStreamExtra] = {1.0f, 0.0f, 0.0f, 0.0f};
         STCHK(S->d_wsp.alloc(cwsp));
-        STCHK(S->d_wss.alloc(wdd::kStreamRecord * cn));
-        bytes += 8 * (cwsp + wdd::kStreamRecord * cn);
+        STCHK(S->d_wss.alloc(nws));
+        STCHK(hipMemcpy(S->d_wss.p + wdd::kStreamRecord * cn, one64, sizeof(one64),
+                        hipMemcpyHostToDevice));
+        bytes += 8 * (cwsp + nws);
         if (fp32) {
             STCHK(S->d_wsp32.alloc(cwsp));
-            STCHK(S->d_wss32.alloc(wdd::kStreamRecord * cn));
-            bytes += 4 * (cwsp + wdd::kStreamRecord * cn);
+            STCHK(S->d_wss32.alloc(nws));
+            STCHK(hipMemcpy(S->d_wss32.p + wdd::kStreamRecord * cn, one32, sizeof(one32),
+                            hipMemcpyHostToDevice));
+            bytes += 4 * (cwsp + nws);
         }
     }
     if (shared) {
@@ -1540,6 +1623,11 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
             STCHK(hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking));
             STCHK(hipEventCreate(&S->sev0[i]));
             STCHK(hipEventCreate(&S->sev1[i]));
+            STCHK(hipEventCreateWithFlags(&S->sevc[i], hipEventDisableTiming));
+            for (int k = 0; k < Store::kSub; ++k) {
+                STCHK(hipStreamCreateWithFlags(&S->gs[i][k], hipStreamNonBlocking));
+                STCHK(hipEventCreateWithFlags(&S->gev[i][k], hipEventDisableTiming));
+            }
         }
         bytes += ci * 32 + nw * (sizeof(wdd::SubDesc) + 4);
     }
@@ -1768,8 +1856,7 @@ int dd_setup(dd_handle** out, const dd_mesh* mesh, int degree, const double* wav
     h->store = S;
     rc = reserve(h, S);
     if (rc == DD_OK) rc = upload(h, ha);
-    if (rc == DD_OK && h->opt.layout == DD_LAYOUT_AUTO && h->layout != DD_LAYOUT_STREAM)
-        rc = autotune_layout(h);
+    if (rc == DD_OK && h->opt.layout == DD_LAYOUT_AUTO) rc = autotune_layout(h);
     if (rc == DD_OK) rc = noalloc_init(h);
     if (rc != DD_OK) {
         dd_destroy(h);
@@ -2159,20 +2246,20 @@ namespace {
 // Layout of a placed problem in a shared store: the store's cached choice
 // for its subdomain shape, else the autotuner's (then cached).
 int choose_layout_shared(dd_handle* h) {
-    if (h->opt.layout != DD_LAYOUT_AUTO || h->layout == DD_LAYOUT_STREAM) return DD_OK;
+    if (h->opt.layout != DD_LAYOUT_AUTO) return DD_OK;
     Store* S = h->store;
     const auto key = std::make_tuple(h->mx, h->my, h->P, h->opt.precision);
     {
         std::lock_guard<std::mutex> lk(S->mu);
         auto it = S->layout_cache.find(key);
         if (it != S->layout_cache.end()) {
-            layout_config(h, it->second);
+            layout_config(h, it->second.first, it->second.second);
             return DD_OK;
         }
     }
     CHK(autotune_layout(h));
     std::lock_guard<std::mutex> lk(S->mu);
-    S->layout_cache[key] = h->layout;
+    S->layout_cache[key] = std::make_pair(h->layout, h->wg);
     return DD_OK;
 }
 

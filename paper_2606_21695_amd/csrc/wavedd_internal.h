@@ -10,7 +10,46 @@ namespace wdd {
 
 constexpr int kMaxP = 4;           // largest supported polynomial degree
 constexpr int kMaxWG = 1024;       // largest workgroup
-constexpr int kStreamRecord = 8;   // Reals per node of the STREAM workspace
+// Reals per node of the STREAM workspace (state triple, coefficient pair,
+// side triple); the workspace then holds the interior record {1, 0, 0}
+// (padded to kStreamExtra Reals).
+constexpr int kStreamRecord = 8;
+constexpr int kStreamExtra = 4;
+
+// WaveHoltz stop rule of one subdomain (Sec. V: the fixed-point iteration
+// runs until its update is small), given the workgroup sums
+// dsum = ||u_new - u||^2 and nsum = ||u_new||^2: stop when
+// dsum <= tau^2 nsum (tau <= 0: never, a fixed count).  Sweeps in FP32 also
+// stop when the update has stagnated at the FP32 rounding floor, whose level
+// depends on how strongly the subdomain amplifies rounding errors: when the
+// update is below kWhStallRel ||u|| and did not shrink over the last
+// iteration, or when it has not improved on its smallest value for
+// kWhStallIters iterations in a row.  Further periods only repeat rounding
+// noise; the FP64 refinement of the outer iteration supplies the accuracy.
+// State: best (smallest dsum so far, start +inf), prev (last dsum, start
+// +inf), stall (iterations since best improved, start 0).  Deterministic:
+// all threads hold the same sums.
+constexpr double kWhStallRel = 1e-4;
+constexpr int kWhStallIters = 8;
+struct WhStall {
+    double best = HUGE_VAL, prev = HUGE_VAL;
+    int stall = 0;
+};
+template <typename Real>
+__device__ __forceinline__ bool wh_stop(double tau, double dsum, double nsum, WhStall& s) {
+    if (!(tau > 0.0)) return false;
+    if (dsum <= tau * tau * nsum) return true;
+    if (sizeof(Real) != 4) return false;
+    const bool flat = dsum <= kWhStallRel * kWhStallRel * nsum && dsum >= s.prev;
+    s.prev = dsum;
+    if (dsum < s.best) {
+        s.best = dsum;
+        s.stall = 0;
+    } else {
+        s.stall += 1;
+    }
+    return flat || s.stall >= kWhStallIters;
+}
 
 // One subdomain work item of a sweep launch.  All offsets index the
 // per-node arrays (node_off) or the interface arrays (if_off, nbr_off).
