@@ -424,80 +424,121 @@ def batch_bench(args):
     print(json.dumps(out))
 
 
+def serve_sample(wl_list, requests, max_nodes, max_sub_nodes):
+    """The first `requests` requests of the seeded stream whose global mesh
+    has at most max_nodes nodes and whose subdomains at most max_sub_nodes."""
+    out = []
+    for wl in wl_list:
+        n = (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1)
+        nl = ((wl.nx // wl.sx) * wl.P + 1) * ((wl.ny // wl.sy) * wl.P + 1)
+        if n <= max_nodes and nl <= max_sub_nodes:
+            out.append(wl)
+        if len(out) == requests:
+            break
+    return out
+
+
 def serve_bench(args):
-    """Serving engine on the first requests of the seeded request stream:
-    closed-loop saturated throughput first, then Poisson arrivals at a
-    fraction rho of it; latency is arrival to result."""
-    import threading
+    """Serving engine on a seeded sample of the request stream (each request
+    its own mesh, degree, frequency, wavespeed and sources; FP32 sweeps with
+    FP64 refinement, tol 1e-6): closed-loop saturated throughput, then
+    Poisson arrivals at fractions rho of it (latency = arrival to result),
+    then the closed loop again under a small HBM budget; beside it the plain
+    FP64 form (one dd_solve at a time) on the first requests of the sample."""
     import torch
     import workloads
     from paper_2606_21695_amd import wavedd as W
     W.require_gpu()
     torch.cuda.set_device(0)
-    # the first requests of the stream whose global mesh has at most
-    # --max-nodes nodes (bounded bench time)
-    wls = [wl for wl in workloads.c5(n_requests=20 * args.requests)
-           if (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1) <= args.max_nodes][:args.requests]
+    wls = serve_sample(workloads.c5(n_requests=args.stream), args.requests, args.max_nodes,
+                       args.max_sub_nodes)
     specs = [W.workload_spec(wl) for wl in wls]
     prec = W.DD_FP64 if args.precision == "fp64" else W.DD_FP32
-    o = W.dd_default_options(precision=prec, tau_in=wls[0].tau_in if prec == W.DD_FP32 else 1e-10,
+    o = W.dd_default_options(precision=prec, tau_in=wls[0].tau_in if prec == W.DD_FP32 else 1e-12,
                              relax=args.relax, max_wh=args.max_wh, tc2=args.tc2)
-    budget = int(args.budget_gib * (1 << 30))
 
-    def run(arrivals):
+    def run(arrivals, budget, tag):
         e = W.dd_engine_create(budget, args.max_active, o)
         try:
-            ids, t_sub = [], []
+            ids = []
             t0 = time.perf_counter()
             for k, s_ in enumerate(specs):
                 if arrivals is not None:
                     dt = arrivals[k] - (time.perf_counter() - t0)
                     if dt > 0:
                         time.sleep(dt)
-                ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 2000))
+                ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 3000))
             res = [None] * len(ids)
             where = {rid: k for k, rid in enumerate(ids)}
-            for _ in ids:
+            for n_done in range(len(ids)):
                 rid = W.dd_engine_wait_any(e)
                 k = where[rid]
                 res[k] = W.dd_engine_wait(e, rid, specs[k]["c"].size, allow_notconv=True)
-                log(f"request {k} ({specs[k]['c'].size} nodes, P={specs[k]['P']}) done: "
-                    f"{res[k][2][2] - res[k][2][0]:.3f} s")
+                log(f"{tag}: request {k} ({specs[k]['c'].size} nodes, P={specs[k]['P']}, "
+                    f"{specs[k]['sx']}x{specs[k]['sy']} subdomains) done, "
+                    f"{n_done + 1}/{len(ids)} at {time.perf_counter() - t0:.1f} s")
             wall = time.perf_counter() - t0
             info = W.dd_engine_get_info(e)
         finally:
             W.dd_engine_destroy(e)
-        return res, wall, info
+        lat = [t[2] - t[0] for _, _, t, _ in res]
+        return {"solves_per_s": len(specs) / wall, "wall_s": wall,
+                "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                               "p99": 1e3 * float(np.percentile(lat, 99))},
+                "dof_updates_per_s": sum(st["dof_updates"] for _, st, _, _ in res) / wall,
+                "launches": info["launches"], "peak_running": info["peak_running"],
+                "not_converged": int(sum(rc != 0 for *_, rc in res)),
+                "max_true_rel_residual": float(max(st["true_rel_residual"] for _, st, _, _ in res))}
 
-    res0, wall0, info0 = run(None)
-    mu = len(specs) / wall0
-    rng = np.random.default_rng(5)
-    arr = np.cumsum(rng.exponential(1.0 / (args.rho * mu), len(specs)))
-    res, wall, info = run(arr)
-    lat = [t[2] - t[0] for _, _, t, _ in res]
-    dof = sum(st["dof_updates"] for _, st, _, _ in res)
+    budget = int(args.budget_gib * (1 << 30))
+    sat = run(None, budget, "closed loop")
+    mu = sat["solves_per_s"]
+    rhos = [float(r) for r in args.rhos.split(",")]
+    at_rho = {}
+    for i, rho in enumerate(rhos):
+        rng = np.random.default_rng(5 + i)
+        arr = np.cumsum(rng.exponential(1.0 / (rho * mu), len(specs)))
+        at_rho[str(rho)] = dict(run(arr, budget, f"rho={rho}"), rho=rho)
+    small = run(None, int(args.small_budget_gib * (1 << 30)), "small budget")
+    # the plain FP64 form: one dd_solve at a time, FP64 sweeps to 1e-12
+    plain_lat = []
+    for k in range(min(args.plain_requests, len(specs))):
+        s_ = specs[k]
+        h = W.dd_setup(s_["nx"], s_["ny"], s_["P"], s_["c"], s_["omega"], s_["sx"], s_["sy"],
+                       s_["x0"], s_["x1"], s_["y0"], s_["y1"],
+                       W.dd_default_options(tau_in=1e-12, max_wh=args.max_wh))
+        try:
+            t0 = time.perf_counter()
+            W.dd_solve(h, s_["f"], None, wls[k].tol, 3000, allow_notconv=True)
+            plain_lat.append(time.perf_counter() - t0)
+        finally:
+            W.dd_destroy(h)
+    n_plain = len(plain_lat)
     out = {
         "metric": "DD solves/s (serving, continuous batching)",
-        "value": len(specs) / wall, "unit": "solves/s", "n_gpus": 1, "steps": len(specs),
-        "warmup": 0, "ms_per_step": 1e3 * wall / len(specs), "higher_is_better": True,
+        "value": mu, "unit": "solves/s", "n_gpus": 1, "steps": len(specs),
+        "warmup": 0, "ms_per_step": 1e3 / mu, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == W.DD_FP64 else "f32 sweep / f64 outer",
         "data": "synthetic (seeded request stream: own mesh, P, omega, wavespeed, sources)",
-        "config": {"workload": f"c5: first {len(specs)} requests of <= {args.max_nodes} nodes, "
-                               f"Poisson arrivals at rho={args.rho} of saturated throughput",
+        "config": {"workload": f"c5: the first {len(specs)} requests of the seeded stream "
+                               f"(seed 5, {args.stream} requests drawn) with at most "
+                               f"{args.max_nodes} global nodes and {args.max_sub_nodes} nodes per "
+                               f"subdomain",
                    "precision": args.precision, "max_active": args.max_active,
-                   "budget_gib": args.budget_gib, "tc2": args.tc2},
-        "saturated_solves_per_s": mu,
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99))},
-        "saturated_latency_ms": {"p50": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 50)),
-                                 "p99": 1e3 * float(np.percentile([t[2] - t[0] for _, _, t, _ in res0], 99))},
-        "dof_updates_per_s": dof / wall,
-        "launches": info["launches"],
-        "peak_running": info["peak_running"],
-        "not_converged": int(sum(rc != 0 for *_, rc in res)),
+                   "budget_gib": args.budget_gib, "tc2": args.tc2, "relax": args.relax},
+        "saturated": sat,
+        "poisson": at_rho,
+        "small_budget": dict(small, budget_gib=args.small_budget_gib),
+        "plain_fp64_single_solves": {
+            "requests": n_plain,
+            "solves_per_s": n_plain / sum(plain_lat) if plain_lat else None,
+            "latency_ms": {"p50": 1e3 * float(np.percentile(plain_lat, 50)),
+                           "p99": 1e3 * float(np.percentile(plain_lat, 99))} if plain_lat else None},
         "request_sizes": {"nodes_min": int(min(s_["c"].size for s_ in specs)),
-                          "nodes_max": int(max(s_["c"].size for s_ in specs))},
+                          "nodes_max": int(max(s_["c"].size for s_ in specs)),
+                          "nodes_total": int(sum(s_["c"].size for s_ in specs)),
+                          "subdomains_total": int(sum(s_["sx"] * s_["sy"] for s_ in specs))},
     }
     print(json.dumps(out))
 
@@ -751,12 +792,22 @@ def main():
                     help="box workloads: full solves instead of the DD-cycle timing")
     ap.add_argument("--box-tol", type=float, default=1e-6,
                     help="outer tolerance of --box-solve")
-    ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--max-nodes", type=int, default=600000,
+    ap.add_argument("--requests", type=int, default=200,
+                    help="serving mode: requests taken from the seeded stream")
+    ap.add_argument("--stream", type=int, default=10000,
+                    help="serving mode: requests drawn from the seeded stream")
+    ap.add_argument("--max-nodes", type=int, default=60000,
                     help="serving mode: skip requests with more global nodes")
-    ap.add_argument("--rho", type=float, default=0.8)
+    ap.add_argument("--max-sub-nodes", type=int, default=10000,
+                    help="serving mode: skip requests with larger subdomains")
+    ap.add_argument("--rhos", default="0.5,0.8,0.95",
+                    help="serving mode: arrival rates as fractions of the saturated rate")
     ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--small-budget-gib", type=float, default=2.0,
+                    help="serving mode: HBM budget of the admission run")
+    ap.add_argument("--plain-requests", type=int, default=20,
+                    help="serving mode: requests solved one at a time in plain FP64")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (a kernel of known "
                          "traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")

@@ -294,7 +294,8 @@ def test_engine_mix_matches_oracle_fp64(gpu_lib):
 
 def test_engine_c5_requests_alone_and_mixed_match_oracle(gpu_lib):
     """Twenty requests drawn (seeded) from the serving stream among those of
-    at most 50,000 global nodes, FP32 sweeps with FP64 refinement, served
+    at most 60,000 global nodes and 5,000 nodes per subdomain, FP32 sweeps
+    with FP64 refinement, served
     together and each alone: every result within 1e-6 of the FP64 oracle DD
     at the same outer tolerance (1e-8 here, so that the bar is tighter than
     the FP32 sweep accuracy), and the mixed result equal to the alone result
@@ -302,7 +303,8 @@ def test_engine_c5_requests_alone_and_mixed_match_oracle(gpu_lib):
     import workloads
     W = gpu_lib
     cand = [wl for wl in workloads.c5(n_requests=2000)
-            if (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1) <= 50000]
+            if (wl.nx * wl.P + 1) * (wl.ny * wl.P + 1) <= 60000
+            and ((wl.nx // wl.sx) * wl.P + 1) * ((wl.ny // wl.sy) * wl.P + 1) <= 5000]
     rng = np.random.default_rng(55)
     pick = [cand[i] for i in sorted(rng.choice(len(cand), 20, replace=False))]
     specs = [W.workload_spec(wl) for wl in pick]

@@ -122,13 +122,16 @@ def lognormal_field(seed, n_modes=32, kmax=4, contrast=3.0):
         for (kx, ky), a, p in zip(ks, amp, ph):
             out += a * np.cos(2 * np.pi * (kx * X + ky * Y) + p)
         return out
-    g = np.linspace(0.0, 1.0, 257)
-    GX, GY = np.meshgrid(g, g)
-    gmax = np.abs(G(GX, GY)).max()
-    scale = 0.5 * np.log(contrast) / gmax
+    # max |G| on a 257^2 grid, computed when the field is first sampled (a
+    # request stream draws many fields and samples few of them)
+    scale = []
 
     def c(X, Y):
-        return np.exp(scale * G(X, Y))
+        if not scale:
+            g = np.linspace(0.0, 1.0, 257)
+            GX, GY = np.meshgrid(g, g)
+            scale.append(0.5 * np.log(contrast) / np.abs(G(GX, GY)).max())
+        return np.exp(scale[0] * G(X, Y))
     c.cmin = float(np.exp(-0.5 * np.log(contrast)))
     return c
 
