@@ -251,7 +251,9 @@ int dd_time_sweep(dd_handle* h, int reps, int fixed_iters, double* ms, double* d
 typedef void (*dd_progress_fn)(void* user, int outer_iters, double rel_residual);
 int dd_set_progress(dd_handle* h, dd_progress_fn fn, void* user, int every);
 
-/* Layout in use (DD_LAYOUT_NODE .. DD_LAYOUT_STREAM) and threads/workgroup. */
+/* Layout in use (DD_LAYOUT_NODE .. DD_LAYOUT_STREAM) and threads per
+ * subdomain: the workgroup size, times the number of workgroups that share
+ * each subdomain when the autotuner gives a STREAM subdomain several. */
 int dd_layout(const dd_handle* h, int* layout, int* wg_threads);
 
 /* Coordinates of the global GLL nodes of a mesh (N each, flat index

@@ -1445,9 +1445,12 @@ struct StreamGeom {
     bool side_col;   // every node of this lane's column reads its side record
     Real wx[2 * P + 1];
 
-    __device__ void setup(int nxl, int nyl, const Real* WT) {
+    // K workgroups share the subdomain; this is number k of them: the waves of
+    // all K are numbered consecutively and split the same way.
+    __device__ void setup(int nxl, int nyl, const Real* WT, int K = 1, int k = 0) {
         constexpr int OW = 64 - 2 * P;
-        const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+        const int tid = threadIdx.x, nw1 = blockDim.x >> 6;
+        const int wave = k * nw1 + (tid >> 6), nwaves = K * nw1;
         lane = tid & 63;
         const int CG = (nxl + OW - 1) / OW;
         const int RS = nwaves / CG;
@@ -1612,11 +1615,77 @@ __device__ __forceinline__ void stream_rows(const StreamGeom<Real, P>& G, const 
     }
 }
 
+// Barrier of the K workgroups that share one STREAM subdomain.  They run on
+// one XCD (the launch places them so and checks it), whose L2 all their CUs
+// share: each wave waits for its own stores to reach L2, one thread per
+// workgroup counts itself in with an L2 atomic and polls until all K have
+// arrived (bounded: after kXBarSpins polls, or when any workgroup of the
+// launch gave up, it sets the launch's abort flag and returns false), then
+// drops the CU's L1 lines so that the next loads see what the other
+// workgroups wrote.  With K = 1 it is a workgroup barrier.
+constexpr int kXBarSpins = 1 << 20;
+
+struct XBar {
+    int* cnt;      // arrivals at this item's barriers
+    int* abort;    // launch-wide abort flag
+    double* part;  // 2 K doubles: per-workgroup partial sums
+    int* flag;     // LDS: this workgroup's verdict of the last barrier
+    int K, k, epoch;
+};
+
+__device__ __forceinline__ bool xbar_sync(XBar& b) {
+    if (b.K == 1) {
+        __syncthreads();
+        return true;
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    b.epoch += 1;
+    if (threadIdx.x == 0) {
+        atomicAdd(b.cnt, 1);
+        const int target = b.epoch * b.K;
+        int ok = 1;
+        for (int spin = 0; atomicAdd(b.cnt, 0) < target; ++spin) {
+            if (spin >= kXBarSpins || atomicAdd(b.abort, 0) != 0) {
+                atomicExch(b.abort, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        asm volatile("buffer_inv sc0" ::: "memory");
+        *b.flag = ok;
+    }
+    __syncthreads();
+    return *b.flag != 0;
+}
+
+// Sum of the K workgroups' partial sums (a, b) in a fixed order, the same
+// in every workgroup; false if the barrier gave up.
+__device__ __forceinline__ bool xbar_sum2(XBar& x, double& a, double& b) {
+    if (x.K == 1) return true;
+    if (threadIdx.x == 0) {
+        x.part[2 * x.k] = a;
+        x.part[2 * x.k + 1] = b;
+    }
+    if (!xbar_sync(x)) return false;
+    a = 0.0;
+    b = 0.0;
+    for (int j = 0; j < x.K; ++j) {
+        a += x.part[2 * j];
+        b += x.part[2 * j + 1];
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool xb_sync_ok(XBar& x) { return xbar_sync(x); }
+
 template <typename Real, int P>
 __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, int item, Real* lds,
-                                  double* red) {
+                                  double* red, XBar& xb) {
     constexpr int W = 2 * P + 1;
-    const int nxl = d.nxl, nyl = d.nyl, tid = threadIdx.x, bd = blockDim.x;
+    const int nxl = d.nxl, nyl = d.nyl, bd = xb.K * (int)blockDim.x;
+    const int tid = xb.k * (int)blockDim.x + (int)threadIdx.x;  // over the K workgroups
     const int nloc = nxl * nyl, stride = nxl + 2 * kMaxP;
     const int di = bd % nxl, dj = bd / nxl;
     stream_tables<Real, P>(lds, A.K1[P]);
@@ -1648,9 +1717,9 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
             if (il >= nxl) { il -= nxl; ++jl; }
         }
     }
-    __syncthreads();
+    if (!xb_sync_ok(xb)) return;
     StreamGeom<Real, P> G;
-    G.setup(nxl, nyl, WT);
+    G.setup(nxl, nyl, WT, xb.K, xb.k);
     G.side_col = all_sides || G.ic == 0 || G.ic == nxl - 1;
     const Real sig = (Real)d.sigma;
     const int nt = d.nt;
@@ -1682,7 +1751,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
         }
         double dsum = 0.0, nsum = 0.0;
         for (int nu = 1; nu < nt; ++nu) {
-            __syncthreads();
+            if (!xb_sync_ok(xb)) return;
             const Real* cur = (nu & 1) ? p1 : p0;
             Real* nxt = (nu & 1) ? p0 : p1;
             if (!G.active) continue;
@@ -1695,12 +1764,14 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
                                            m > 0 || warm, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
+        if (!xbar_sum2(xb, dsum, nsum)) return;
         it = m + 1;
         if (!(dsum == dsum)) break;
         if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
     }
     __threadfence_block();
-    __syncthreads();
+    if (!xb_sync_ok(xb)) return;
+    if (xb.k != 0) return;
     exchange(A, d);
     if (threadIdx.x == 0) A.wh_iters[item] = it;
 }
@@ -1710,11 +1781,42 @@ __global__ void __launch_bounds__(kStreamWG) sweep_stream_kernel(const SweepArgs
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    XBar xb{nullptr, nullptr, nullptr, nullptr, 1, 0, 0};
     for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
         const SubDesc d = A.desc[item];
-        sweep_stream_item<Real, P>(A, d, item, lds, red);
+        sweep_stream_item<Real, P>(A, d, item, lds, red, xb);
         __syncthreads();
     }
+}
+
+// The STREAM sweep with K = A.xb_k workgroups per item.  The hardware hands
+// out the workgroups of a launch to the XCDs in turn (workgroup b to XCD
+// b mod 8), so item i takes workgroups (i / 8) * 8K + 8k + i mod 8,
+// k < K: all on one XCD.  Each workgroup checks that at the start (it
+// publishes its XCD number and compares after the first barrier) and the
+// launch aborts if they differ; the host then runs the plain STREAM sweep.
+template <typename Real, int P>
+__global__ void __launch_bounds__(kStreamWG) sweep_stream_coop_kernel(const SweepArgs<Real> A) {
+    extern __shared__ double smem_d[];
+    double* red = smem_d;
+    Real* lds = reinterpret_cast<Real*>(smem_d + 40);
+    const int K = A.xb_k, b = blockIdx.x;
+    const int item = (b / (8 * K)) * 8 + b % 8, k = (b / 8) % K;
+    if (item >= A.n_items) return;
+    XBar xb{A.xb_cnt + item, A.xb_abort, A.xb_part + 2 * (size_t)K * item,
+            reinterpret_cast<int*>(smem_d + 36), K, k, 0};
+    // placement check: every workgroup of the item on the same XCD
+    const int xcc = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // HW_REG_XCC_ID
+    if (threadIdx.x == 0) xb.part[2 * k] = (double)(xcc + 1);
+    if (!xbar_sync(xb)) return;
+    for (int j = 0; j < K; ++j)
+        if (xb.part[2 * j] != (double)(xcc + 1)) {
+            if (threadIdx.x == 0) atomicExch(xb.abort, 1);
+            return;
+        }
+    if (!xbar_sync(xb)) return;  // all have read the placement before part is reused
+    const SubDesc d = A.desc[item];
+    sweep_stream_item<Real, P>(A, d, item, lds, red, xb);
 }
 
 // q = A p per subdomain (node-indexed, unpadded; the windows are bounds
@@ -1914,6 +2016,27 @@ hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStrea
 }
 
 template <typename Real>
+hipError_t launch_sweep_stream_coop(const SweepArgs<Real>& a, int P, int wg, hipStream_t s) {
+    const size_t lds = a.lds_bytes;
+    const int K = a.xb_k;
+    if (wg > kStreamWG || K < 2 || !a.xb_cnt || !a.xb_abort || !a.xb_part)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(((a.n_items + 7) / 8) * 8 * K);
+    SweepArgs<Real> arg = a;
+    void* args[] = {&arg};
+#define L(PP)                                                                                 \
+    {                                                                                         \
+        hipError_t e = hipLaunchCooperativeKernel(                                            \
+            reinterpret_cast<const void*>(&sweep_stream_coop_kernel<Real, PP>), dim3(grid),  \
+            dim3(wg), args, (unsigned)lds, s);                                                \
+        if (e != hipSuccess) return e;                                                        \
+    }
+    WDD_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <typename Real>
 hipError_t launch_apply_stream(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
                                hipStream_t s) {
     const size_t lds = a.lds_bytes;
@@ -1927,6 +2050,10 @@ hipError_t launch_apply_stream(const SweepArgs<Real>& a, int P, int wg, const Re
 
 template hipError_t launch_sweep_stream<double>(const SweepArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_sweep_stream<float>(const SweepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_sweep_stream_coop<double>(const SweepArgs<double>&, int, int,
+                                                     hipStream_t);
+template hipError_t launch_sweep_stream_coop<float>(const SweepArgs<float>&, int, int,
+                                                    hipStream_t);
 template hipError_t launch_apply_stream<double>(const SweepArgs<double>&, int, int, const double*,
                                                 double*, hipStream_t);
 template hipError_t launch_apply_stream<float>(const SweepArgs<float>&, int, int, const float*,

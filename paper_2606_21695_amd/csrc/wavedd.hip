@@ -339,6 +339,12 @@ struct dd_handle {
     std::vector<wdd::SubDesc> desc;  // global offsets into the store
     int layout = DD_LAYOUT_PATCH, wg = 256;
     size_t lds[2] = {0, 0};          // dynamic LDS of a launch, FP64 / FP32
+    // STREAM sweeps of a handle of its own may share each subdomain among
+    // xb_k workgroups (1: one workgroup per subdomain); d_xb holds their
+    // per-item counters, the abort flag and the per-item partial sums
+    int xb_k = 1;
+    DBuf<char> d_xb;
+    size_t xb_bytes = 0;
     int dev = 0;
     hipStream_t stream = nullptr;
     // placement in the store
@@ -518,6 +524,50 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
 // One sweep launch of this handle alone: g_out = sweep(g_in, src), u =
 // subdomain solutions.  In a shared store the vectors pass through the
 // handle's range of the exchange buffers.
+// Per-item counters (int), the abort flag and the per-item partial sums
+// (2 K doubles) of the shared-subdomain STREAM sweep, laid out in d_xb.
+template <typename Real>
+void xb_args(dd_handle* h, wdd::SweepArgs<Real>& a) {
+    char* base = h->d_xb.p;
+    const size_t cnt_bytes = (((size_t)h->L + 1) * sizeof(int) + 255) & ~(size_t)255;
+    a.xb_k = h->xb_k;
+    a.xb_cnt = reinterpret_cast<int*>(base);
+    a.xb_abort = reinterpret_cast<int*>(base) + h->L;
+    a.xb_part = reinterpret_cast<double*>(base + cnt_bytes);
+}
+
+size_t xb_bytes_for(int64_t L, int K) {
+    const size_t cnt_bytes = (((size_t)L + 1) * sizeof(int) + 255) & ~(size_t)255;
+    return cnt_bytes + sizeof(double) * 2 * (size_t)K * (size_t)L;
+}
+
+// One sweep launch in the handle's layout; STREAM sweeps of a shared-
+// subdomain handle (xb_k > 1) that start cold go to the cooperative kernel,
+// and if that launch is refused or aborts (its workgroups could not be
+// placed together) the handle falls back to one workgroup per subdomain
+// and relaunches the plain kernel on the same inputs.
+template <typename Real>
+int launch_sweep(dd_handle* h, const double2* gi, double2* go, double src, bool with_f,
+                 double tau, int max_wh, hipStream_t s) {
+    wdd::SweepArgs<Real> a = make_args<Real>(h, gi, go, src, with_f, tau, max_wh);
+    if (h->layout == DD_LAYOUT_STREAM && h->xb_k > 1 && !h->sweep_warm) {
+        xb_args(h, a);
+        HIPCHK(hipMemsetAsync(h->d_xb.p, 0, h->xb_bytes, s));
+        hipError_t e = wdd::launch_sweep_stream_coop<Real>(a, h->P, h->wg, s);
+        int aborted = 1;
+        if (e == hipSuccess) {
+            HIPCHK(hipMemcpyAsync(&aborted, a.xb_abort, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            (void)hipGetLastError();
+        }
+        if (!aborted) return DD_OK;
+        h->xb_k = 1;
+    }
+    HIPCHK(launch_layout<Real>(h->layout, a, h->P, h->wg, s));
+    return DD_OK;
+}
+
 int run_sweep_direct(dd_handle* h, const double2* g_in, double2* g_out, double src, bool with_f,
                      bool timed, int prec, double tau, int max_wh) {
     hipStream_t s = h->stream;
@@ -531,14 +581,10 @@ int run_sweep_direct(dd_handle* h, const double2* g_in, double2* g_out, double s
         go = S->d_gout.p;
     }
     if (timed) HIPCHK(hipEventRecord(h->ev0, s));
-    hipError_t e;
     if (prec == DD_FP32)
-        e = launch_layout<float>(h->layout, make_args<float>(h, gi, go, src, with_f, tau, max_wh),
-                                 h->P, h->wg, s);
+        CHK(launch_sweep<float>(h, gi, go, src, with_f, tau, max_wh, s));
     else
-        e = launch_layout<double>(h->layout, make_args<double>(h, gi, go, src, with_f, tau, max_wh),
-                                  h->P, h->wg, s);
-    HIPCHK(e);
+        CHK(launch_sweep<double>(h, gi, go, src, with_f, tau, max_wh, s));
     if (timed) HIPCHK(hipEventRecord(h->ev1, s));
     if (S->shared)
         HIPCHK(hipMemcpyAsync(g_out, S->d_gout.p + h->if_base, sizeof(double2) * h->n_if,
@@ -1198,6 +1244,22 @@ wdd::OperatorArgs op_args(const dd_handle* h) {
 // Layout autotuner: time every layout that fits on this problem (two
 // fixed-count WaveHoltz iterations per subdomain, zero data: the kernels
 // have no data-dependent work) and keep the fastest.
+// Workgroups per subdomain for a STREAM sweep of a handle of its own: the
+// largest K in {4, 2} with K workgroups of 512 threads per subdomain still
+// resident together (one per CU), when the device supports cooperative
+// launches; 1 otherwise.
+int stream_share_k(const dd_handle* h) {
+    int coop = 0, cus = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->dev) != hipSuccess)
+        return 1;
+    if (!coop) return 1;
+    const int64_t items = (h->L + 7) / 8 * 8;
+    for (int k : {4, 2})
+        if (items * k <= cus) return k;
+    return 1;
+}
+
 // Layout and workgroup size of a subdomain shape, by timing: three sweeps
 // of two WaveHoltz iterations each with every candidate that fits.  The
 // candidates are the on-chip layouts (one element patch per thread with two
@@ -1207,31 +1269,47 @@ wdd::OperatorArgs op_args(const dd_handle* h) {
 // columns per wave, the rows of a column group split over the waves).
 int autotune_layout(dd_handle* h) {
     struct Cand {
-        int layout, wg;
+        int layout, wg, k;
     };
     std::vector<Cand> cands;
     if (h->layout == DD_LAYOUT_STREAM) {
-        for (int wg : stream_wg_options(h)) cands.push_back({DD_LAYOUT_STREAM, wg});
+        for (int wg : stream_wg_options(h)) cands.push_back({DD_LAYOUT_STREAM, wg, 1});
+        // a handle of its own with few subdomains may share each subdomain
+        // among several workgroups (all resident at once: at most one
+        // 512-thread workgroup per CU)
+        const int k = h->store->shared ? 1 : stream_share_k(h);
+        if (k > 1) cands.push_back({DD_LAYOUT_STREAM, 512, k});
     } else {
         for (int lay : {DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_NODE})
-            if (layout_fits(h, lay)) cands.push_back({lay, layout_threads(h, lay)});
+            if (layout_fits(h, lay)) cands.push_back({lay, layout_threads(h, lay), 1});
     }
-    Cand best{h->layout, h->wg};
+    Cand best{h->layout, h->wg, 1};
     double best_ms = 1e300;
     for (const Cand& c : cands) {
         layout_config(h, c.layout, c.wg);
+        if (c.k > 1) {
+            if (h->xb_bytes < xb_bytes_for(h->L, c.k)) {
+                h->d_xb.free();
+                HIPCHK(h->d_xb.alloc(xb_bytes_for(h->L, c.k)));
+                h->xb_bytes = xb_bytes_for(h->L, c.k);
+            }
+        }
+        h->xb_k = c.k;
         HIPCHK(hipMemsetAsync(h->d_g0.p, 0, sizeof(double2) * h->n_if, h->stream));
         CHK(run_sweep(h, h->d_g0.p, h->d_tmp.p, 0.0, false, false, h->opt.precision, 0.0, 2));
         reset_stats(h);
         for (int r = 0; r < 3; ++r)
             CHK(run_sweep(h, h->d_g0.p, h->d_tmp.p, 0.0, false, true, h->opt.precision, 0.0, 2));
         const double ms = h->st.sweep_seconds;
-        if (ms < best_ms) {
+        // a shared-subdomain candidate that fell back to one workgroup
+        // (h->xb_k reset by launch_sweep) is not kept
+        if (ms < best_ms && h->xb_k == c.k) {
             best_ms = ms;
             best = c;
         }
     }
     layout_config(h, best.layout, best.wg);
+    h->xb_k = best.k;
     reset_stats(h);
     return DD_OK;
 }
@@ -1664,6 +1742,7 @@ void unplace(dd_handle* h) {
     h->d_fre.free(); h->d_fim.free(); h->d_gre.free(); h->d_gim.free(); h->d_ure.free();
     h->d_uim.free(); h->d_wxg.free(); h->d_wyg.free(); h->d_Mg.free(); h->d_Hg.free();
     h->d_work.free();
+    h->d_xb.free();
     wdd::blas_free(h->blas);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
@@ -1941,7 +2020,7 @@ int dd_set_progress(dd_handle* h, dd_progress_fn fn, void* user, int every) {
 int dd_layout(const dd_handle* h, int* layout, int* wg) {
     CHK(validate_handle(h));
     if (layout) *layout = h->layout;
-    if (wg) *wg = h->wg;
+    if (wg) *wg = h->wg * (h->layout == DD_LAYOUT_STREAM ? h->xb_k : 1);
     return DD_OK;
 }
 

@@ -26,10 +26,13 @@ constexpr int kStreamExtra = 4;
 // iteration, or when it has not improved on its smallest value for
 // kWhStallIters iterations in a row.  Further periods only repeat rounding
 // noise; the FP64 refinement of the outer iteration supplies the accuracy.
+// Either way the update must already be below kWhStallGate ||u||, so a
+// subdomain that is still converging slowly is never cut short.
 // State: best (smallest dsum so far, start +inf), prev (last dsum, start
 // +inf), stall (iterations since best improved, start 0).  Deterministic:
 // all threads hold the same sums.
 constexpr double kWhStallRel = 1e-4;
+constexpr double kWhStallGate = 1e-3;
 constexpr int kWhStallIters = 8;
 struct WhStall {
     double best = HUGE_VAL, prev = HUGE_VAL;
@@ -48,7 +51,7 @@ __device__ __forceinline__ bool wh_stop(double tau, double dsum, double nsum, Wh
     } else {
         s.stall += 1;
     }
-    return flat || s.stall >= kWhStallIters;
+    return flat || (s.stall >= kWhStallIters && dsum <= kWhStallGate * kWhStallGate * nsum);
 }
 
 // One subdomain work item of a sweep launch.  All offsets index the
@@ -107,6 +110,14 @@ struct SweepArgs {
     Real* ws_p;              // STREAM layout: padded p grids (2 per subdomain, at desc.ws_off)
     Real* ws_s;              // STREAM layout: 4 Reals per node of state, then 4 of coefficients
     int64_t ws_stride;       // node capacity of ws_s
+    // STREAM layout shared by several workgroups (sweep_stream_coop_kernel):
+    // xb_k workgroups per item, per-item arrival counters, a launch-wide abort
+    // flag and per-item stop-test partial sums (2 * xb_k doubles each); all
+    // zeroed before the launch.
+    int xb_k;
+    int* xb_cnt;
+    int* xb_abort;
+    double* xb_part;
     size_t lds_bytes;        // dynamic LDS per workgroup of the launch
     int nt_max;              // largest N_t of the launch (sizes the LDS tables)
     double K1[kMaxP + 1][kMaxP + 1][kMaxP + 1];  // K1[P][a][b]: reference D^T W D
@@ -130,6 +141,10 @@ hipError_t launch_apply_node(const SweepArgs<Real>& a, int P, int wg, const Real
                              hipStream_t s);
 template <typename Real>
 hipError_t launch_sweep_stream(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
+// The STREAM sweep with a.xb_k workgroups per item (a cooperative launch, so
+// all workgroups are resident together); the caller checks *a.xb_abort.
+template <typename Real>
+hipError_t launch_sweep_stream_coop(const SweepArgs<Real>& a, int P, int wg, hipStream_t s);
 template <typename Real>
 hipError_t launch_apply_stream(const SweepArgs<Real>& a, int P, int wg, const Real* p, Real* q,
                                hipStream_t s);
