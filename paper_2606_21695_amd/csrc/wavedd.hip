@@ -798,6 +798,15 @@ void sched_leave(Store* S) {
     S->sched.active -= 1;
 }
 
+// Cost of one posted sweep: its slowest work item (subdomain nodes x steps
+// per period x WaveHoltz iterations of its last sweep).
+double sweep_cost(const SweepReq* r) {
+    double c = 0.0;
+    for (int64_t l = 0; l < r->h->L; ++l) c = std::max(c, item_cost(r->h, l));
+    return c;
+}
+constexpr double kRoundCostSpan = 4.0;
+
 // A sweep of a batched handle: post it; if a launch slot is free, launch
 // everything pending (this sweep included unless another thread already
 // took it), else wait for the launch that carries it.
@@ -820,9 +829,20 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
             Q.cv.wait(lk);
             continue;
         }
-        std::vector<SweepReq*> batch;
-        batch.swap(Q.pending);
+        // One round takes the oldest pending sweep and every other pending
+        // sweep of a similar cost (its slowest subdomain within a factor of
+        // four): a round lasts as long as its slowest work item, so mixing
+        // cheap and expensive requests would hold the cheap ones to the pace
+        // of the expensive ones.  The rest wait for the next free slot.
+        std::vector<SweepReq*> batch, rest;
+        const double c0 = sweep_cost(Q.pending.front());
+        for (SweepReq* r : Q.pending) {
+            const double c = sweep_cost(r);
+            (c <= kRoundCostSpan * c0 && c * kRoundCostSpan >= c0 ? batch : rest).push_back(r);
+        }
+        Q.pending.swap(rest);
         Q.busy[slot] = true;
+        if (!Q.pending.empty()) Q.cv.notify_all();   // another free slot can take them
         lk.unlock();
         const int rc = launch_batch(S, batch, slot);
         const std::string msg = rc == DD_OK ? std::string() : g_err;
