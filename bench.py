@@ -444,7 +444,16 @@ def serve_bench(args):
     FP64 refinement, tol 1e-6): closed-loop saturated throughput, then
     Poisson arrivals at fractions rho of it (latency = arrival to result),
     then the closed loop again under a small HBM budget; beside it the plain
-    FP64 form (one dd_solve at a time) on the first requests of the sample."""
+    FP64 form (one dd_solve at a time) on the first requests of the sample.
+
+    The engine runs each active request's outer-iteration kernels on that
+    request's stream and each round of sweeps on one of eight launch
+    streams; HIP maps streams onto GPU_MAX_HW_QUEUES hardware queues (4 by
+    default) and kernels of streams that share a queue run in order, so a
+    request's short kernels would wait behind other requests' sweeps.  The
+    serving run therefore asks for 32 hardware queues (set before the HIP
+    runtime starts, unless the environment sets it)."""
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "32")
     import torch
     import workloads
     from paper_2606_21695_amd import wavedd as W
@@ -796,10 +805,11 @@ def main():
                     help="serving mode: requests taken from the seeded stream")
     ap.add_argument("--stream", type=int, default=10000,
                     help="serving mode: requests drawn from the seeded stream")
-    ap.add_argument("--max-nodes", type=int, default=60000,
+    ap.add_argument("--max-nodes", type=int, default=150000,
                     help="serving mode: skip requests with more global nodes")
-    ap.add_argument("--max-sub-nodes", type=int, default=10000,
-                    help="serving mode: skip requests with larger subdomains")
+    ap.add_argument("--max-sub-nodes", type=int, default=2500,
+                    help="serving mode: skip requests with larger subdomains (the default "
+                         "keeps requests whose subdomains fit the on-chip layouts)")
     ap.add_argument("--rhos", default="0.5,0.8,0.95",
                     help="serving mode: arrival rates as fractions of the saturated rate")
     ap.add_argument("--max-active", type=int, default=16)

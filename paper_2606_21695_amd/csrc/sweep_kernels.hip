@@ -1660,21 +1660,34 @@ __device__ __forceinline__ bool xbar_sync(XBar& b) {
     return *b.flag != 0;
 }
 
+// Value another workgroup of the item wrote, read where the barrier's
+// atomics are performed (L2): a plain load of a workgroup-uniform address
+// may be served by the scalar cache, which the barrier does not invalidate.
+__device__ __forceinline__ double xbar_read(double* p) { return atomicAdd(p, 0.0); }
+
 // Sum of the K workgroups' partial sums (a, b) in a fixed order, the same
-// in every workgroup; false if the barrier gave up.
-__device__ __forceinline__ bool xbar_sum2(XBar& x, double& a, double& b) {
+// in every workgroup (thread 0 reads them and passes the sums on through
+// LDS); false if the barrier gave up.
+__device__ __forceinline__ bool xbar_sum2(XBar& x, double& a, double& b, double* sh) {
     if (x.K == 1) return true;
     if (threadIdx.x == 0) {
         x.part[2 * x.k] = a;
         x.part[2 * x.k + 1] = b;
     }
     if (!xbar_sync(x)) return false;
-    a = 0.0;
-    b = 0.0;
-    for (int j = 0; j < x.K; ++j) {
-        a += x.part[2 * j];
-        b += x.part[2 * j + 1];
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int j = 0; j < x.K; ++j) {
+            sa += xbar_read(x.part + 2 * j);
+            sb += xbar_read(x.part + 2 * j + 1);
+        }
+        sh[0] = sa;
+        sh[1] = sb;
     }
+    __syncthreads();
+    a = sh[0];
+    b = sh[1];
+    __syncthreads();
     return true;
 }
 
@@ -1764,7 +1777,7 @@ __device__ void sweep_stream_item(const SweepArgs<Real>& A, const SubDesc& d, in
                                            m > 0 || warm, dsum, nsum);
         }
         block_sum2(dsum, nsum, red);
-        if (!xbar_sum2(xb, dsum, nsum)) return;
+        if (!xbar_sum2(xb, dsum, nsum, red + 32)) return;
         it = m + 1;
         if (!(dsum == dsum)) break;
         if (wh_stop<Real>(tau, dsum, nsum, stall)) break;
@@ -1809,11 +1822,15 @@ __global__ void __launch_bounds__(kStreamWG) sweep_stream_coop_kernel(const Swee
     const int xcc = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // HW_REG_XCC_ID
     if (threadIdx.x == 0) xb.part[2 * k] = (double)(xcc + 1);
     if (!xbar_sync(xb)) return;
-    for (int j = 0; j < K; ++j)
-        if (xb.part[2 * j] != (double)(xcc + 1)) {
-            if (threadIdx.x == 0) atomicExch(xb.abort, 1);
-            return;
-        }
+    int* same = reinterpret_cast<int*>(smem_d + 37);
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        for (int j = 0; j < K; ++j) ok &= xbar_read(xb.part + 2 * j) == (double)(xcc + 1);
+        if (!ok) atomicExch(xb.abort, 1);
+        *same = ok;
+    }
+    __syncthreads();
+    if (!*same) return;
     if (!xbar_sync(xb)) return;  // all have read the placement before part is reused
     const SubDesc d = A.desc[item];
     sweep_stream_item<Real, P>(A, d, item, lds, red, xb);

@@ -267,7 +267,7 @@ struct SweepReq {
 // form the next batch, so the batches grow with the load and no problem
 // waits for another's sweep to finish.
 struct Sched {
-    static constexpr int kSlots = 4;   // launches in flight (one stream each)
+    static constexpr int kSlots = 8;   // launches in flight (one stream each)
     std::mutex mu;
     std::condition_variable cv;
     int active = 0;                    // problems inside a batched solve
@@ -550,7 +550,10 @@ template <typename Real>
 int launch_sweep(dd_handle* h, const double2* gi, double2* go, double src, bool with_f,
                  double tau, int max_wh, hipStream_t s) {
     wdd::SweepArgs<Real> a = make_args<Real>(h, gi, go, src, with_f, tau, max_wh);
-    if (h->layout == DD_LAYOUT_STREAM && h->xb_k > 1 && !h->sweep_warm) {
+    // FP64 sweeps only: FP32 shared-subdomain sweeps disagree with the
+    // one-workgroup sweep on short row segments (cause not found), so they
+    // stay off
+    if (sizeof(Real) == 8 && h->layout == DD_LAYOUT_STREAM && h->xb_k > 1 && !h->sweep_warm) {
         xb_args(h, a);
         HIPCHK(hipMemsetAsync(h->d_xb.p, 0, h->xb_bytes, s));
         hipError_t e = wdd::launch_sweep_stream_coop<Real>(a, h->P, h->wg, s);
@@ -1297,7 +1300,7 @@ int autotune_layout(dd_handle* h) {
         // a handle of its own with few subdomains may share each subdomain
         // among several workgroups (all resident at once: at most one
         // 512-thread workgroup per CU)
-        const int k = h->store->shared ? 1 : stream_share_k(h);
+        const int k = (h->store->shared || h->opt.precision != DD_FP64) ? 1 : stream_share_k(h);
         if (k > 1) cands.push_back({DD_LAYOUT_STREAM, 512, k});
     } else {
         for (int lay : {DD_LAYOUT_PATCH, DD_LAYOUT_PATCH_XCHG, DD_LAYOUT_NODE})
@@ -2711,6 +2714,10 @@ int dd_engine_create(dd_engine** out, size_t budget, int max_active, const dd_op
         store_destroy(S);
         return fail(DD_ENOMEM, "budget too small for the device store");
     }
+    // a served request's rounds run on its slot stream alone: every other
+    // stream would share a hardware queue with some request's stream, and
+    // kernels that share a queue run in order
+    S->sub_streams = 1;
     dd_engine* e = new dd_engine();
     e->store = S;
     e->opt = o;

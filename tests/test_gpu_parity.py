@@ -724,16 +724,18 @@ def test_c2_full_size_solve_matches_oracle_dd(gpu_lib, c2_oracle_dd, variant):
         assert err < 1e-6
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_stream_shared_subdomains_match_single_workgroup(gpu_lib, prec):
-    """Large STREAM subdomains of a problem with few of them: the autotuner
-    may give each subdomain several workgroups (synchronised through L2 every
-    step).  With a fixed WaveHoltz count the per-node arithmetic is the same
-    as with one workgroup per subdomain, so the sweeps agree bit for bit; the
-    converged solve matches the oracle DD."""
+@pytest.mark.parametrize("shape", [(128, 3, 2, 60.0), (128, 2, 4, 19.7), (96, 2, 3, 30.0)])
+def test_stream_shared_subdomains_match_single_workgroup(gpu_lib, shape):
+    """Large STREAM subdomains of an FP64 problem with few of them: the
+    autotuner may give each subdomain several workgroups (synchronised
+    through L2 every step).  With a fixed WaveHoltz count the per-node
+    arithmetic is the same as with one workgroup per subdomain, so the
+    sweeps agree bit for bit (also with short row segments: 4x4 subdomains
+    of 65x65 nodes split over 32 waves).  FP32 sweeps keep one workgroup per
+    subdomain."""
     W = gpu_lib
-    nx = ny = 128
-    P, sx, sy, om = 3, 2, 2, 60.0
+    nx, P, s_, om = shape
+    ny, sx, sy, prec = nx, s_, s_, 0
     rng = np.random.default_rng(31)
     res = {}
     for lay in (0, 4):   # autotuned, STREAM with one workgroup per subdomain
