@@ -491,24 +491,31 @@ def serve_bench(args):
         finally:
             W.dd_engine_destroy(e)
         lat = [t[2] - t[0] for _, _, t, _ in res]
-        return {"solves_per_s": len(specs) / wall, "wall_s": wall,
+        out = {"solves_per_s": len(specs) / wall, "wall_s": wall,
                 "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                                "p99": 1e3 * float(np.percentile(lat, 99))},
                 "dof_updates_per_s": sum(st["dof_updates"] for _, st, _, _ in res) / wall,
                 "launches": info["launches"], "peak_running": info["peak_running"],
                 "not_converged": int(sum(rc != 0 for *_, rc in res)),
                 "max_true_rel_residual": float(max(st["true_rel_residual"] for _, st, _, _ in res))}
+        log(f"{tag}: " + json.dumps(out))
+        return out
 
     budget = int(args.budget_gib * (1 << 30))
-    sat = run(None, budget, "closed loop")
-    mu = sat["solves_per_s"]
-    rhos = [float(r) for r in args.rhos.split(",")]
+    if args.mu > 0:
+        # saturated rate given (measured by an earlier closed-loop run)
+        sat, mu = None, args.mu
+    else:
+        sat = run(None, budget, "closed loop")
+        mu = sat["solves_per_s"]
+    rhos = [float(r) for r in args.rhos.split(",") if r]
     at_rho = {}
     for i, rho in enumerate(rhos):
         rng = np.random.default_rng(5 + i)
         arr = np.cumsum(rng.exponential(1.0 / (rho * mu), len(specs)))
         at_rho[str(rho)] = dict(run(arr, budget, f"rho={rho}"), rho=rho)
-    small = run(None, int(args.small_budget_gib * (1 << 30)), "small budget")
+    small = (run(None, int(args.small_budget_gib * (1 << 30)), "small budget")
+             if args.small_budget_gib > 0 else None)
     # the plain FP64 form: one dd_solve at a time, FP64 sweeps to 1e-12
     plain_lat = []
     for k in range(min(args.plain_requests, len(specs))):
@@ -520,6 +527,7 @@ def serve_bench(args):
             t0 = time.perf_counter()
             W.dd_solve(h, s_["f"], None, wls[k].tol, 3000, allow_notconv=True)
             plain_lat.append(time.perf_counter() - t0)
+            log(f"plain FP64: request {k} ({s_['c'].size} nodes) {plain_lat[-1]:.2f} s")
         finally:
             W.dd_destroy(h)
     n_plain = len(plain_lat)
@@ -537,8 +545,9 @@ def serve_bench(args):
                    "precision": args.precision, "max_active": args.max_active,
                    "budget_gib": args.budget_gib, "tc2": args.tc2, "relax": args.relax},
         "saturated": sat,
+        "saturated_solves_per_s": mu,
         "poisson": at_rho,
-        "small_budget": dict(small, budget_gib=args.small_budget_gib),
+        "small_budget": dict(small, budget_gib=args.small_budget_gib) if small else None,
         "plain_fp64_single_solves": {
             "requests": n_plain,
             "solves_per_s": n_plain / sum(plain_lat) if plain_lat else None,
@@ -803,9 +812,12 @@ def main():
                     help="outer tolerance of --box-solve")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving mode: requests taken from the seeded stream")
-    ap.add_argument("--stream", type=int, default=10000,
+    ap.add_argument("--stream", type=int, default=20000,
                     help="serving mode: requests drawn from the seeded stream")
-    ap.add_argument("--max-nodes", type=int, default=150000,
+    ap.add_argument("--mu", type=float, default=0.0,
+                    help="serving mode: saturated solves/s from an earlier closed-loop run "
+                         "(skips the closed loop)")
+    ap.add_argument("--max-nodes", type=int, default=80000,
                     help="serving mode: skip requests with more global nodes")
     ap.add_argument("--max-sub-nodes", type=int, default=2500,
                     help="serving mode: skip requests with larger subdomains (the default "

@@ -1641,11 +1641,12 @@ void store_destroy(Store* S) {
 
 // Allocate a store with the given capacities (entries per index space).
 int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int64_t ct,
-                 int64_t cw, int64_t cwsp, bool fp32, bool shared) {
+                 int64_t cw, int64_t cwsp, bool fp32, bool shared, int sub_streams = Store::kSub) {
     *out = nullptr;
     Store* S = new Store();
     S->dev = dev;
     S->shared = shared;
+    S->sub_streams = std::max(1, std::min(sub_streams, Store::kSub));
     S->align = shared ? 64 : 1;
     S->cap_node = cn;
     S->cap_if = ci;
@@ -1725,7 +1726,7 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
             STCHK(hipEventCreate(&S->sev0[i]));
             STCHK(hipEventCreate(&S->sev1[i]));
             STCHK(hipEventCreateWithFlags(&S->sevc[i], hipEventDisableTiming));
-            for (int k = 0; k < Store::kSub; ++k) {
+            for (int k = 0; k < S->sub_streams && S->sub_streams > 1; ++k) {
                 STCHK(hipStreamCreateWithFlags(&S->gs[i][k], hipStreamNonBlocking));
                 STCHK(hipEventCreateWithFlags(&S->gev[i][k], hipEventDisableTiming));
             }
@@ -2709,15 +2710,15 @@ int dd_engine_create(dd_engine** out, size_t budget, int max_active, const dd_op
     const int64_t ci = cn / 2, cit = std::max<int64_t>(1024, cn / 64);
     const int64_t ct = std::max<int64_t>(1 << 16, cn / 16), cw = 1 << 18, cwsp = cn * 5 / 2;
     Store* S = nullptr;
-    CHK(store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, o.precision == DD_FP32, true));
+    // a served request's rounds run on its slot stream alone and the store
+    // creates no group streams: HIP maps streams onto a fixed pool of
+    // hardware queues, every further stream would share a queue with some
+    // request's stream, and kernels that share a queue run in order
+    CHK(store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, o.precision == DD_FP32, true, 1));
     if (S->bytes >= budget) {
         store_destroy(S);
         return fail(DD_ENOMEM, "budget too small for the device store");
     }
-    // a served request's rounds run on its slot stream alone: every other
-    // stream would share a hardware queue with some request's stream, and
-    // kernels that share a queue run in order
-    S->sub_streams = 1;
     dd_engine* e = new dd_engine();
     e->store = S;
     e->opt = o;
