@@ -516,14 +516,20 @@ def serve_bench(args):
         at_rho[str(rho)] = dict(run(arr, budget, f"rho={rho}"), rho=rho)
     small = (run(None, int(args.small_budget_gib * (1 << 30)), "small budget")
              if args.small_budget_gib > 0 else None)
-    # the plain FP64 form: one dd_solve at a time, FP64 sweeps to 1e-12
+    # the plain FP64 form: one dd_solve at a time, FP64 sweeps to 1e-12, on
+    # the first requests of the sample (no new solve after --plain-budget-s)
     plain_lat = []
+    t_plain = time.perf_counter()
     for k in range(min(args.plain_requests, len(specs))):
+        if time.perf_counter() - t_plain > args.plain_budget_s:
+            break
         s_ = specs[k]
         h = W.dd_setup(s_["nx"], s_["ny"], s_["P"], s_["c"], s_["omega"], s_["sx"], s_["sy"],
                        s_["x0"], s_["x1"], s_["y0"], s_["y1"],
                        W.dd_default_options(tau_in=1e-12, max_wh=args.max_wh))
         try:
+            W.dd_set_progress(h, lambda it, rel, k=k: log(f"plain FP64: request {k}: "
+                                                          f"{it} matvecs, residual {rel:.2e}"), 25)
             t0 = time.perf_counter()
             W.dd_solve(h, s_["f"], None, wls[k].tol, 3000, allow_notconv=True)
             plain_lat.append(time.perf_counter() - t0)
@@ -549,7 +555,7 @@ def serve_bench(args):
         "poisson": at_rho,
         "small_budget": dict(small, budget_gib=args.small_budget_gib) if small else None,
         "plain_fp64_single_solves": {
-            "requests": n_plain,
+            "requests": n_plain, "budget_s": args.plain_budget_s,
             "solves_per_s": n_plain / sum(plain_lat) if plain_lat else None,
             "latency_ms": {"p50": 1e3 * float(np.percentile(plain_lat, 50)),
                            "p99": 1e3 * float(np.percentile(plain_lat, 99))} if plain_lat else None},
@@ -812,12 +818,14 @@ def main():
                     help="outer tolerance of --box-solve")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving mode: requests taken from the seeded stream")
-    ap.add_argument("--stream", type=int, default=20000,
+    ap.add_argument("--stream", type=int, default=40000,
                     help="serving mode: requests drawn from the seeded stream")
+    ap.add_argument("--plain-budget-s", type=float, default=150.0,
+                    help="serving mode: no new plain FP64 solve after this many seconds")
     ap.add_argument("--mu", type=float, default=0.0,
                     help="serving mode: saturated solves/s from an earlier closed-loop run "
                          "(skips the closed loop)")
-    ap.add_argument("--max-nodes", type=int, default=80000,
+    ap.add_argument("--max-nodes", type=int, default=40000,
                     help="serving mode: skip requests with more global nodes")
     ap.add_argument("--max-sub-nodes", type=int, default=2500,
                     help="serving mode: skip requests with larger subdomains (the default "

@@ -239,11 +239,10 @@ __device__ __forceinline__ void sweep3_items(const Sweep3Args<Real>& A) {
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
-    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        const Sub3 d = A.desc[item];
-        sweep3_item<Real, P>(A, d, item, lds, red);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;   // one workgroup per item (grid = n_items)
+    if (item >= A.n_items) return;
+    const Sub3 d = A.desc[item];   // loaded once: kept in registers across the stores below
+    sweep3_item<Real, P>(A, d, item, lds, red);
 }
 
 template <typename Real, int P>

@@ -206,6 +206,13 @@ __device__ double2 side_stiffness(const SweepArgs<Real>& A, const double2* u, in
 // it adds 2 (q K_side u - omega^2 m u / c^2) / W_side, m = q W_side plus
 // q^2/2 at an end whose other side is an interface as well.  Cooperative
 // over the workgroup, coalesced along sides.
+// Receiving slot of side s (a select over constant indices: a per-lane
+// index into the descriptor would put the workgroup's copy of it in
+// scratch memory).
+__device__ __forceinline__ int64_t side_nbr(const SubDesc& d, int s) {
+    return s == 0 ? d.nbr_off[0] : s == 1 ? d.nbr_off[1] : s == 2 ? d.nbr_off[2] : d.nbr_off[3];
+}
+
 template <typename Real>
 __device__ void exchange(const SweepArgs<Real>& A, const SubDesc& d) {
     const int nxl = d.nxl, nyl = d.nyl;
@@ -221,7 +228,7 @@ __device__ void exchange(const SweepArgs<Real>& A, const SubDesc& d) {
         } else {
             s = 3; pos = k - 2 * nyl - nxl; node = (nyl - 1) * nxl + pos;
         }
-        const int64_t dst = d.nbr_off[s];
+        const int64_t dst = side_nbr(d, s);
         if (dst >= 0) {
             const double2 g = A.g_in[d.if_off + k];
             const double K = A.kside[d.if_off + k];
@@ -234,8 +241,8 @@ __device__ void exchange(const SweepArgs<Real>& A, const SubDesc& d) {
                 const double W = A.w1d[d.w_off + (vert ? nxl + pos : pos)];
                 double m = q * W;
                 // the sides meeting this one at its first / last node
-                if (pos == 0 && d.nbr_off[vert ? 2 : 0] >= 0) m += 0.5 * q * q;
-                if (pos == n - 1 && d.nbr_off[vert ? 3 : 1] >= 0) m += 0.5 * q * q;
+                if (pos == 0 && side_nbr(d, vert ? 2 : 0) >= 0) m += 0.5 * q * q;
+                if (pos == n - 1 && side_nbr(d, vert ? 3 : 1) >= 0) m += 0.5 * q * q;
                 const int64_t base = d.node_off + (vert ? (s == 0 ? 0 : nxl - 1) : (s == 2 ? 0 : (int64_t)(nyl - 1) * nxl));
                 const double2 Ku = side_stiffness(A, A.u, base, vert ? nxl : 1, pos,
                                                   vert ? d.my : d.mx, d.P,
@@ -732,11 +739,10 @@ __global__ void __launch_bounds__(WG) sweep_patch_kernel(const SweepArgs<Real> A
     extern __shared__ double smem_d[];
     double* red = smem_d;                       // 2 * 16 doubles
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
-    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        const SubDesc d = A.desc[item];
-        sweep_patch_item<Real, P, HAS_SRC>(A, d, item, lds, red);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;   // one workgroup per item (grid = n_items)
+    if (item >= A.n_items) return;
+    const SubDesc d = A.desc[item];   // loaded once: kept in registers across the stores below
+    sweep_patch_item<Real, P, HAS_SRC>(A, d, item, lds, red);
 }
 
 // q = A p on stacked subdomain vectors with the patch routines of the
@@ -1163,11 +1169,10 @@ __global__ void __launch_bounds__(WG) sweep_patch1_kernel(const SweepArgs<Real> 
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
-    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        const SubDesc d = A.desc[item];
-        sweep_patch1_item<Real, P, WG, HAS_SRC>(A, d, item, lds, red);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;   // one workgroup per item (grid = n_items)
+    if (item >= A.n_items) return;
+    const SubDesc d = A.desc[item];   // loaded once: kept in registers across the stores below
+    sweep_patch1_item<Real, P, WG, HAS_SRC>(A, d, item, lds, red);
 }
 
 // q = A p with the one-barrier patch routines (test path).
@@ -1356,11 +1361,10 @@ __global__ void __launch_bounds__(kMaxWG) sweep_node_kernel(const SweepArgs<Real
     extern __shared__ double smem_d[];
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
-    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        const SubDesc d = A.desc[item];
-        sweep_node_item<Real, P>(A, d, item, lds, red);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;   // one workgroup per item (grid = n_items)
+    if (item >= A.n_items) return;
+    const SubDesc d = A.desc[item];   // loaded once: kept in registers across the stores below
+    sweep_node_item<Real, P>(A, d, item, lds, red);
 }
 
 template <typename Real, int P>
@@ -1795,11 +1799,10 @@ __global__ void __launch_bounds__(kStreamWG) sweep_stream_kernel(const SweepArgs
     double* red = smem_d;
     Real* lds = reinterpret_cast<Real*>(smem_d + 40);
     XBar xb{nullptr, nullptr, nullptr, nullptr, 1, 0, 0};
-    for (int item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-        const SubDesc d = A.desc[item];
-        sweep_stream_item<Real, P>(A, d, item, lds, red, xb);
-        __syncthreads();
-    }
+    const int item = blockIdx.x;   // one workgroup per item (grid = n_items)
+    if (item >= A.n_items) return;
+    const SubDesc d = A.desc[item];   // loaded once: kept in registers across the stores below
+    sweep_stream_item<Real, P>(A, d, item, lds, red, xb);
 }
 
 // The STREAM sweep with K = A.xb_k workgroups per item.  The hardware hands
