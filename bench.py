@@ -34,16 +34,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector ALU peaks
 # kernel's code (its layout section plus the shared helpers, comments
 # ignored) and the run; reported as null once that code changes.
 MEASURED_TRAFFIC = {
-    ("15aca0d8531ab9fe", "solve", "c2", "fp64"): round((19782.4 * 2.0 + 32432.0) * 1024),
-    ("d577db17b639aa2c", "protocol", "c3", "fp64"): round((57468569.1 * 2.0 + 63332868.5) * 1024),
-    ("d577db17b639aa2c", "protocol", "c3", "fp32"): round((28815929.2 * 2.0 + 31884724.0) * 1024),
+    ("7b4a3859ee1e88a9", "solve", "c2", "fp64"): round((15405.7 * 2.0 + 15651.4) * 1024),
+    ("6a3c53d4b8a9ebae", "protocol", "c3", "fp64"): round((40715903.3 * 2.0 + 50894355.0) * 1024),
 }
 
 # HBM bytes per launch of the box (3D) sweep kernel, same counters and scale,
 # keyed by the hash of the box kernel source (comments ignored).
 MEASURED_TRAFFIC3 = {
-    ("b5d79508330583c9", "c6", "fp64"): round((754258.0 * 2.0 + 1754764.2) * 1024),
-    ("b5d79508330583c9", "c6", "fp32"): round((332686.2 * 2.0 + 333535.6) * 1024),
+    ("92c1ab59dbfb4a70", "c6", "fp64"): round((473142.4 * 2.0 + 437807.2) * 1024),
 }
 
 # section markers of each layout in the kernel source
@@ -53,6 +51,14 @@ _SECTIONS = {1: ("// NODE layout (one DOF per thread)", "// STREAM layout"),
              4: ("// STREAM layout", "}  // namespace\n")}
 LAYOUT_NAMES = {1: "node", 2: "patch", 3: "patch_xchg", 4: "stream"}
 LAYOUT_IDS = {"auto": 0, **{v: k for k, v in LAYOUT_NAMES.items()}}
+
+
+def kernel_name(lay, wg):
+    """Kernel a layout runs; a STREAM subdomain of more than one workgroup
+    (threads per subdomain above 1024) runs the cooperative build."""
+    if lay == 4 and wg > 1024:
+        return "sweep_stream_coop_kernel"
+    return KERNEL_NAMES[lay]
 KERNEL_NAMES = {1: "sweep_node_kernel", 2: "sweep_patch1_kernel", 3: "sweep_patch_kernel",
                 4: "sweep_stream_kernel"}
 
@@ -745,7 +751,7 @@ def protocol_bench(args):
         traffic = MEASURED_TRAFFIC.get((kernel_hash(lay), "protocol", args.config, args.precision))
         prob.close()
         layout = LAYOUT_NAMES[lay]
-        kernel = KERNEL_NAMES[lay]
+        kernel = kernel_name(lay, wg)
         desc = (f"{args.config}: {wl.nx}x{wl.ny} elements P={wl.P}, {wl.sx}x{wl.sy} subdomains, "
                 f"omega={wl.omega:.2f}")
         flop = flops_per_update(wl.P) * dof
@@ -832,7 +838,7 @@ def main():
                          "keeps requests whose subdomains fit the on-chip layouts)")
     ap.add_argument("--rhos", default="0.5,0.8,0.95",
                     help="serving mode: arrival rates as fractions of the saturated rate")
-    ap.add_argument("--max-active", type=int, default=16)
+    ap.add_argument("--max-active", type=int, default=24)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--small-budget-gib", type=float, default=2.0,
                     help="serving mode: HBM budget of the admission run")
@@ -942,7 +948,7 @@ def main():
         "roofline": dict(roof, **{
             "traffic": MEASURED_TRAFFIC.get((kernel_hash(lay), "solve", args.config,
                                              args.precision)),
-            "kernel": KERNEL_NAMES[lay],
+            "kernel": kernel_name(lay, wg),
             "flop_per_dof_update": fl,
             "avg_launch_ms": 1e3 * sweep_s / sweeps if sweeps else None}),
     }

@@ -267,7 +267,7 @@ struct SweepReq {
 // form the next batch, so the batches grow with the load and no problem
 // waits for another's sweep to finish.
 struct Sched {
-    static constexpr int kSlots = 8;   // launches in flight (one stream each)
+    static constexpr int kSlots = 32;  // most work-list staging regions (rounds in flight)
     std::mutex mu;
     std::condition_variable cv;
     int active = 0;                    // problems inside a batched solve
@@ -306,7 +306,9 @@ struct Store {
     DBuf<int> d_work_iters;
     wdd::SubDesc* h_work = nullptr;  // pinned staging of the work lists (per slot)
     int* h_work_iters = nullptr;
-    hipStream_t ss[Sched::kSlots] = {};   // launch slot streams (shared stores)
+    int n_slots = 0;                      // slots in use (shared stores)
+    int64_t slot_items = 0;               // work-list entries per slot
+    hipStream_t ss[Sched::kSlots] = {};   // launch streams of the slots (batch stores)
     hipEvent_t sev0[Sched::kSlots] = {}, sev1[Sched::kSlots] = {};
     // the launch groups of one slot's round run concurrently on sub-streams:
     // sevc (work list staged) starts them, gev (group done) joins them
@@ -642,8 +644,8 @@ double item_cost(const dd_handle* h, int64_t l) {
 // source); each group is one launch whose work list is sorted by cost,
 // longest first (the hardware dispatches workgroups in order, so the list
 // is the schedule).  Groups run concurrently on the store's group streams.
-int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double* ms_out = nullptr,
-                 int* groups_out = nullptr) {
+int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, hipStream_t s,
+                 double* ms_out = nullptr, int* groups_out = nullptr) {
     HIPCHK(hipSetDevice(S->dev));
     struct Item {
         double cost;
@@ -678,13 +680,13 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
         gg.nt_max = std::max(gg.nt_max, h->nt_max);
         for (int64_t l = 0; l < h->L; ++l) gg.items.push_back({item_cost(h, l), r, l});
     }
-    wdd::SubDesc* hw = S->h_work + (int64_t)slot * S->cap_item;
-    int* hi = S->h_work_iters + (int64_t)slot * S->cap_item;
-    wdd::SubDesc* dw = S->d_work.p + (int64_t)slot * S->cap_item;
-    int* di = S->d_work_iters.p + (int64_t)slot * S->cap_item;
+    wdd::SubDesc* hw = S->h_work + (int64_t)slot * S->slot_items;
+    int* hi = S->h_work_iters + (int64_t)slot * S->slot_items;
+    wdd::SubDesc* dw = S->d_work.p + (int64_t)slot * S->slot_items;
+    int* di = S->d_work_iters.p + (int64_t)slot * S->slot_items;
     int64_t total = 0;
     for (const auto& kv : groups) total += (int64_t)kv.second.items.size();
-    if (total > S->cap_item) return fail(DD_EINVAL, "batched work list exceeds the store");
+    if (total > S->slot_items) return fail(DD_EINVAL, "batched work list exceeds its slot");
     total = 0;
     for (auto& kv : groups) {
         Group& g = kv.second;
@@ -704,7 +706,6 @@ int launch_batch(Store* S, const std::vector<SweepReq*>& reqs, int slot, double*
             g.lds = std::max(g.lds, lds_for(reqs[it.r]->h, g.prec, g.wg, g.nt_max));
         total += (int64_t)g.items.size();
     }
-    hipStream_t s = S->ss[slot];
     HIPCHK(hipEventRecord(S->sev0[slot], s));
     HIPCHK(hipMemcpyAsync(dw, hw, sizeof(wdd::SubDesc) * total, hipMemcpyHostToDevice, s));
     for (const SweepReq* q : reqs)
@@ -823,7 +824,7 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
     Q.pending.push_back(&req);
     while (!req.done) {
         int slot = -1;
-        for (int k = 0; k < Sched::kSlots; ++k)
+        for (int k = 0; k < S->n_slots; ++k)
             if (!Q.busy[k]) {
                 slot = k;
                 break;
@@ -836,18 +837,29 @@ int sched_sweep(dd_handle* h, const double2* g_in, double2* g_out, double src, b
         // sweep of a similar cost (its slowest subdomain within a factor of
         // four): a round lasts as long as its slowest work item, so mixing
         // cheap and expensive requests would hold the cheap ones to the pace
-        // of the expensive ones.  The rest wait for the next free slot.
+        // of the expensive ones.  The rest wait for the next free slot (as
+        // do sweeps beyond the slot's work-list entries).
         std::vector<SweepReq*> batch, rest;
         const double c0 = sweep_cost(Q.pending.front());
+        int64_t items = 0;
         for (SweepReq* r : Q.pending) {
             const double c = sweep_cost(r);
-            (c <= kRoundCostSpan * c0 && c * kRoundCostSpan >= c0 ? batch : rest).push_back(r);
+            const bool fits = batch.empty() || items + r->h->L <= S->slot_items;
+            if (fits && c <= kRoundCostSpan * c0 && c * kRoundCostSpan >= c0) {
+                batch.push_back(r);
+                items += r->h->L;
+            } else {
+                rest.push_back(r);
+            }
         }
         Q.pending.swap(rest);
         Q.busy[slot] = true;
         if (!Q.pending.empty()) Q.cv.notify_all();   // another free slot can take them
         lk.unlock();
-        const int rc = launch_batch(S, batch, slot);
+        // the round runs on the launching thread's stream (the slot's own
+        // stream in a batch store), so rounds in flight are limited by the
+        // staging slots, not by a fixed set of streams
+        const int rc = launch_batch(S, batch, slot, S->ss[slot] ? S->ss[slot] : h->stream);
         const std::string msg = rc == DD_OK ? std::string() : g_err;
         lk.lock();
         for (SweepReq* r : batch) {
@@ -1640,13 +1652,21 @@ void store_destroy(Store* S) {
 }
 
 // Allocate a store with the given capacities (entries per index space).
+// A shared store has n_slots work-list regions of slot_items entries; with
+// slot_streams each slot launches on a stream of its own (and sub_streams
+// group streams), else a round runs on the stream of the thread that
+// launches it.
 int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int64_t ct,
-                 int64_t cw, int64_t cwsp, bool fp32, bool shared, int sub_streams = Store::kSub) {
+                 int64_t cw, int64_t cwsp, bool fp32, bool shared, int sub_streams = Store::kSub,
+                 int n_slots = 8, int64_t slot_items = 0, bool slot_streams = true) {
     *out = nullptr;
     Store* S = new Store();
     S->dev = dev;
     S->shared = shared;
-    S->sub_streams = std::max(1, std::min(sub_streams, Store::kSub));
+    S->sub_streams = slot_streams ? std::max(1, std::min(sub_streams, Store::kSub)) : 1;
+    S->n_slots = std::max(1, std::min(n_slots, Sched::kSlots));
+    S->slot_items = slot_items > 0 ? std::min(slot_items, std::max<int64_t>(cit, 1))
+                                   : std::max<int64_t>(cit, 1);
     S->align = shared ? 64 : 1;
     S->cap_node = cn;
     S->cap_if = ci;
@@ -1716,13 +1736,13 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
     if (shared) {
         STCHK(S->d_gin.alloc(ci));
         STCHK(S->d_gout.alloc(ci));
-        const int64_t nw = Sched::kSlots * std::max<int64_t>(cit, 1);
+        const int64_t nw = (int64_t)S->n_slots * S->slot_items;
         STCHK(S->d_work.alloc(nw));
         STCHK(S->d_work_iters.alloc(nw));
         STCHK(hipHostMalloc((void**)&S->h_work, sizeof(wdd::SubDesc) * nw));
         STCHK(hipHostMalloc((void**)&S->h_work_iters, sizeof(int) * nw));
-        for (int i = 0; i < Sched::kSlots; ++i) {
-            STCHK(hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking));
+        for (int i = 0; i < S->n_slots; ++i) {
+            if (slot_streams) STCHK(hipStreamCreateWithFlags(&S->ss[i], hipStreamNonBlocking));
             STCHK(hipEventCreate(&S->sev0[i]));
             STCHK(hipEventCreate(&S->sev1[i]));
             STCHK(hipEventCreateWithFlags(&S->sevc[i], hipEventDisableTiming));
@@ -2564,13 +2584,13 @@ int dd_batch_time_sweep(dd_batch* b, int reps, int fixed_iters, double* ms, doub
     }
     std::vector<SweepReq*> rp;
     for (auto& r : reqs) rp.push_back(&r);
-    CHK(launch_batch(S, rp, 0));
+    CHK(launch_batch(S, rp, 0, S->ss[0]));
     for (dd_handle* h : b->probs) reset_stats(h);
     double total_ms = 0.0;
     int groups = 0;
     for (int r = 0; r < reps; ++r) {
         double m = 0.0;
-        CHK(launch_batch(S, rp, 0, &m, &groups));
+        CHK(launch_batch(S, rp, 0, S->ss[0], &m, &groups));
         total_ms += m;
     }
     *ms = total_ms / reps;
@@ -2710,11 +2730,16 @@ int dd_engine_create(dd_engine** out, size_t budget, int max_active, const dd_op
     const int64_t ci = cn / 2, cit = std::max<int64_t>(1024, cn / 64);
     const int64_t ct = std::max<int64_t>(1 << 16, cn / 16), cw = 1 << 18, cwsp = cn * 5 / 2;
     Store* S = nullptr;
-    // a served request's rounds run on its slot stream alone and the store
-    // creates no group streams: HIP maps streams onto a fixed pool of
-    // hardware queues, every further stream would share a queue with some
-    // request's stream, and kernels that share a queue run in order
-    CHK(store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, o.precision == DD_FP32, true, 1));
+    // The store creates no streams: a round runs on the stream of the
+    // request that launches it (one stream per running request).  HIP maps
+    // streams onto a fixed pool of hardware queues and kernels that share a
+    // queue run in order, so every further stream would make some request's
+    // short outer-iteration kernels wait behind another request's sweep;
+    // and a fixed set of launch streams would let a few long rounds hold
+    // all of them while cheap requests wait.  32 work-list slots of an
+    // eighth of the work-item space each.
+    CHK(store_create(&S, dev, cn, ci, cit, ct, cw, cwsp, o.precision == DD_FP32, true, 1,
+                     Sched::kSlots, std::max<int64_t>(2048, cit / 8), false));
     if (S->bytes >= budget) {
         store_destroy(S);
         return fail(DD_ENOMEM, "budget too small for the device store");
@@ -2768,7 +2793,7 @@ int dd_engine_submit(dd_engine* e, const dd_problem* prob, const double* f_re, c
         problem_ranges(r->h, S->align);
         r->bytes = problem_own_bytes(r->h) + sizeof(double) * (10 * (size_t)N + 2 * (size_t)r->h->n_trace);
         if (r->h->node_len > S->cap_node || r->h->if_len > S->cap_if ||
-            r->h->item_len > S->cap_item || r->h->tab_len > S->cap_tab ||
+            r->h->item_len > S->cap_item || r->h->L > S->slot_items || r->h->tab_len > S->cap_tab ||
             r->h->wsp_len > S->cap_wsp || r->bytes + S->bytes > e->budget)
             rc = fail(DD_ENOMEM, "request needs more device memory than the engine holds");
     }
