@@ -475,23 +475,43 @@ def serve_bench(args):
     def run(arrivals, budget, tag):
         e = W.dd_engine_create(budget, args.max_active, o)
         try:
-            ids = []
+            import threading
+            where, submitted, errs, lock = {}, threading.Semaphore(0), [], threading.Lock()
             t0 = time.perf_counter()
-            for k, s_ in enumerate(specs):
-                if arrivals is not None:
-                    dt = arrivals[k] - (time.perf_counter() - t0)
-                    if dt > 0:
-                        time.sleep(dt)
-                ids.append(W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 3000))
-            res = [None] * len(ids)
-            where = {rid: k for k, rid in enumerate(ids)}
-            for n_done in range(len(ids)):
+
+            def submit_all():
+                # arrivals on a thread of their own, so that results are
+                # collected (and logged) while requests still arrive
+                try:
+                    for k, s_ in enumerate(specs):
+                        if arrivals is not None:
+                            dt = arrivals[k] - (time.perf_counter() - t0)
+                            if dt > 0:
+                                time.sleep(dt)
+                        with lock:
+                            where[W.dd_engine_submit(e, s_, s_["f"], wls[k].tol, 3000)] = k
+                        submitted.release()
+                except Exception as ex:   # reported by the collecting thread
+                    errs.append(ex)
+                    for _ in range(len(specs)):
+                        submitted.release()
+
+            th = threading.Thread(target=submit_all)
+            th.start()
+            res = [None] * len(specs)
+            for n_done in range(len(specs)):
+                submitted.acquire()
+                if errs:
+                    th.join()
+                    raise errs[0]
                 rid = W.dd_engine_wait_any(e)
-                k = where[rid]
+                with lock:
+                    k = where[rid]
                 res[k] = W.dd_engine_wait(e, rid, specs[k]["c"].size, allow_notconv=True)
                 log(f"{tag}: request {k} ({specs[k]['c'].size} nodes, P={specs[k]['P']}, "
                     f"{specs[k]['sx']}x{specs[k]['sy']} subdomains) done, "
-                    f"{n_done + 1}/{len(ids)} at {time.perf_counter() - t0:.1f} s")
+                    f"{n_done + 1}/{len(specs)} at {time.perf_counter() - t0:.1f} s")
+            th.join()
             wall = time.perf_counter() - t0
             info = W.dd_engine_get_info(e)
         finally:

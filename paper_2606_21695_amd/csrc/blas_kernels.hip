@@ -247,18 +247,22 @@ hipError_t blas_sum2(Blas& b, const double2* v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t blas_init(Blas& b, int max_vecs, hipStream_t) {
+hipError_t blas_init(Blas& b, int max_vecs, hipStream_t s, bool pooled) {
     b.max_blocks = kMaxBlocks;
     b.max_vecs = max_vecs;
-    hipError_t e = hipMalloc(&b.partial, sizeof(double2) * (size_t)kMaxBlocks * max_vecs);
+    b.as = pooled ? s : nullptr;
+    const size_t np = sizeof(double2) * (size_t)kMaxBlocks * max_vecs, nr = sizeof(double2) * (size_t)max_vecs;
+    hipError_t e = b.as ? hipMallocAsync(reinterpret_cast<void**>(&b.partial), np, b.as)
+                        : hipMalloc(&b.partial, np);
     if (e != hipSuccess) return e;
-    return hipMalloc(&b.result, sizeof(double2) * (size_t)max_vecs);
+    return b.as ? hipMallocAsync(reinterpret_cast<void**>(&b.result), nr, b.as) : hipMalloc(&b.result, nr);
 }
 
 void blas_free(Blas& b) {
-    if (b.partial) (void)hipFree(b.partial);
-    if (b.result) (void)hipFree(b.result);
+    if (b.partial) (void)(b.as ? hipFreeAsync(b.partial, b.as) : hipFree(b.partial));
+    if (b.result) (void)(b.as ? hipFreeAsync(b.result, b.as) : hipFree(b.result));
     b.partial = b.result = nullptr;
+    b.as = nullptr;
 }
 
 hipError_t blas_multidot(Blas& b, const double2* V, int64_t ld, int k, const double2* w, int64_t n,

@@ -186,18 +186,26 @@ double wref(const Gll& g, int il, int m) {
     return s;
 }
 
+// Device array.  With a stream (`as`) it comes from the device's
+// stream-ordered memory pool and is returned to it on that stream: hipFree
+// waits for the whole device to go idle, which a served request finishing
+// while other requests' sweeps run must not do.
 template <typename T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
-    hipError_t alloc(size_t count) {
+    hipStream_t as = nullptr;
+    hipError_t alloc(size_t count, hipStream_t s = nullptr) {
         n = count;
-        return hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1));
+        as = s;
+        const size_t bytes = sizeof(T) * std::max<size_t>(count, 1);
+        return s ? hipMallocAsync(reinterpret_cast<void**>(&p), bytes, s) : hipMalloc(&p, bytes);
     }
     void free() {
-        if (p) (void)hipFree(p);
+        if (p) (void)(as ? hipFreeAsync(p, as) : hipFree(p));
         p = nullptr;
         n = 0;
+        as = nullptr;
     }
 };
 
@@ -1235,15 +1243,24 @@ int stage_source(dd_handle* h, const double* d_fre, const double* d_fim) {
 
 double2* u_dev(const dd_handle* h) { return h->store->d_u.p + h->node_base; }
 
+// Stream whose pool a problem's own vectors come from: its stream when it
+// sits in a shared store (batches, served requests), none (plain hipMalloc)
+// for a handle with a store of its own.
+hipStream_t pool_stream(const dd_handle* h) {
+    return (h->store && h->store->shared) ? h->stream : nullptr;
+}
+
 int ensure_staging(dd_handle* h) {
     if (!h->d_fre.p) {
-        HIPCHK(h->d_fre.alloc(h->N));
-        HIPCHK(h->d_fim.alloc(h->N));
-        HIPCHK(h->d_gre.alloc(h->n_trace));
-        HIPCHK(h->d_gim.alloc(h->n_trace));
-        HIPCHK(h->d_ure.alloc(h->N));
-        HIPCHK(h->d_uim.alloc(h->N));
-        HIPCHK(h->d_work.alloc(2 * h->N));
+        hipStream_t as = pool_stream(h);
+        HIPCHK(h->d_fre.alloc(h->N, as));
+        HIPCHK(h->d_fim.alloc(h->N, as));
+        HIPCHK(h->d_gre.alloc(h->n_trace, as));
+        HIPCHK(h->d_gim.alloc(h->n_trace, as));
+        HIPCHK(h->d_ure.alloc(h->N, as));
+        HIPCHK(h->d_uim.alloc(h->N, as));
+        HIPCHK(h->d_work.alloc(2 * h->N, as));
+        if (as) HIPCHK(hipStreamSynchronize(as));
     }
     return DD_OK;
 }
@@ -1734,6 +1751,14 @@ int store_create(Store** out, int dev, int64_t cn, int64_t ci, int64_t cit, int6
         }
     }
     if (shared) {
+        // problems placed in this store take their own vectors from the
+        // device's stream-ordered pool: keep freed memory in the pool (no
+        // release to the system, which would synchronise)
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            STCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+        }
         STCHK(S->d_gin.alloc(ci));
         STCHK(S->d_gout.alloc(ci));
         const int64_t nw = (int64_t)S->n_slots * S->slot_items;
@@ -1886,20 +1911,24 @@ int upload(dd_handle* h, const HostArrays& ha) {
     }
     const int64_t Nx = h->Nx, Ny = h->Ny, N = h->N;
     h->ld = ((h->n_if + 63) / 64) * 64;
-    HIPCHK(h->d_V.alloc((size_t)(h->opt.restart + 1) * h->ld));
-    HIPCHK(h->d_G.alloc(h->n_if));
-    HIPCHK(h->d_h.alloc(h->n_if));
-    HIPCHK(h->d_tmp.alloc(h->n_if));
-    HIPCHK(h->d_g0.alloc(h->n_if));
-    HIPCHK(h->d_r.alloc(h->n_if));
-    HIPCHK(h->d_D.alloc(h->n_if));
-    HIPCHK(h->d_res.alloc(h->n_if));
-    HIPCHK(h->d_coefs.alloc(h->opt.restart + 1));
-    HIPCHK(h->d_wxg.alloc(Nx));
-    HIPCHK(h->d_wyg.alloc(Ny));
-    HIPCHK(h->d_Mg.alloc(N));
-    HIPCHK(h->d_Hg.alloc(N));
-    HIPCHK(wdd::blas_init(h->blas, h->opt.restart + 2, h->stream));
+    // a problem in a shared store takes its own vectors from the stream-
+    // ordered pool (returned without a device-wide wait when it retires)
+    hipStream_t as = pool_stream(h);
+    HIPCHK(h->d_V.alloc((size_t)(h->opt.restart + 1) * h->ld, as));
+    HIPCHK(h->d_G.alloc(h->n_if, as));
+    HIPCHK(h->d_h.alloc(h->n_if, as));
+    HIPCHK(h->d_tmp.alloc(h->n_if, as));
+    HIPCHK(h->d_g0.alloc(h->n_if, as));
+    HIPCHK(h->d_r.alloc(h->n_if, as));
+    HIPCHK(h->d_D.alloc(h->n_if, as));
+    HIPCHK(h->d_res.alloc(h->n_if, as));
+    HIPCHK(h->d_coefs.alloc(h->opt.restart + 1, as));
+    HIPCHK(h->d_wxg.alloc(Nx, as));
+    HIPCHK(h->d_wyg.alloc(Ny, as));
+    HIPCHK(h->d_Mg.alloc(N, as));
+    HIPCHK(h->d_Hg.alloc(N, as));
+    HIPCHK(wdd::blas_init(h->blas, h->opt.restart + 2, h->stream, as != nullptr));
+    if (as) HIPCHK(hipStreamSynchronize(as));   // allocations complete before other streams use them
     h->own_bytes = problem_own_bytes(h);
     h->iters_host.assign(L, 0);
     h->last_iters.assign(L, 1);

@@ -162,8 +162,11 @@ struct Blas {
     double2* partial = nullptr;   // [max_blocks * (max_vecs)] complex partial sums
     double2* result = nullptr;    // [max_vecs] reduced results
     int max_blocks = 0, max_vecs = 0;
+    hipStream_t as = nullptr;     // stream of the pool the buffers came from, or none
 };
-hipError_t blas_init(Blas& b, int max_vecs, hipStream_t s);
+// With pooled, the buffers come from the stream-ordered pool on s (and go
+// back to it on s), else from hipMalloc.
+hipError_t blas_init(Blas& b, int max_vecs, hipStream_t s, bool pooled = false);
 void blas_free(Blas& b);
 // h[i] = <V_i, w> for i < k (V_i = V + i*ld), conjugate-linear in V_i.
 hipError_t blas_multidot(Blas& b, const double2* V, int64_t ld, int k, const double2* w, int64_t n,
