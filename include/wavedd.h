@@ -270,12 +270,13 @@ int dd_mesh_coords(const dd_mesh* mesh, int degree, double* x, double* y);
  * as the subdomains of one problem do (Sec. VI: all subdomains of a sweep in
  * one kernel launch).  A batch places its problems in one device store; each
  * problem runs its own FP64 outer iteration on its own host thread and posts
- * its sweeps; whenever one of four launch slots is free, every pending sweep
- * goes into one batched launch (per launch configuration: precision, degree,
- * layout, workgroup class) whose work list is ordered by estimated cost
- * (DOFs x (N_t - 1) x WaveHoltz iterations of the previous sweep), longest
- * first.  Sweeps posted while the slots are busy form the next batch, so
- * batches grow with the load and no problem waits for another's sweep.
+ * its sweeps; whenever one of eight launch slots is free, the oldest pending
+ * sweep and the pending sweeps of similar cost (slowest subdomain within a
+ * factor of four) go into one round: one launch per launch configuration
+ * (precision, degree, layout, workgroup class) whose work list is ordered by
+ * estimated cost (DOFs x (N_t - 1) x WaveHoltz iterations of the previous
+ * sweep), longest first.  Sweeps posted while the slots are busy form the
+ * next round, so rounds grow with the load.
  * Layouts are autotuned once per subdomain shape (mx, my, P, precision).
  * ------------------------------------------------------------------------ */
 typedef struct dd_batch dd_batch;
@@ -345,9 +346,12 @@ int dd_batch_launches(const dd_batch* b, int64_t* launches);
  * a first-fit allocator), the rest pays for the per-request outer-iteration
  * vectors.  Each running request advances its own FP64 outer iteration on
  * its own host thread and stream; its sweeps share batched launches with
- * the other running requests' (as for dd_batch_solve), and requests join and
- * retire between launches.  Results stay with the engine
- * until dd_engine_wait collects them.
+ * the other running requests' (rounds formed as for dd_batch_solve, up to 32
+ * in flight, each on the stream of the request that launches it), and
+ * requests join and retire between launches.  A request's own vectors come
+ * from the device's stream-ordered memory pool (hipMallocAsync), which the
+ * engine sets to keep freed memory.  Results stay with the engine until
+ * dd_engine_wait collects them.
  * ------------------------------------------------------------------------ */
 typedef struct dd_engine dd_engine;
 

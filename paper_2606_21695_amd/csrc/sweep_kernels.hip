@@ -1633,7 +1633,7 @@ struct XBar {
     int* cnt;      // arrivals at this item's barriers
     int* abort;    // launch-wide abort flag
     double* part;  // 2 K doubles: per-workgroup partial sums
-    int* flag;     // LDS: this workgroup's verdict of the last barrier
+    int* flag;     // LDS: this workgroup's outcome of the last barrier
     int K, k, epoch;
 };
 
