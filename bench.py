@@ -624,10 +624,16 @@ def flops_per_update3(P):
 
 
 def box_bench(args):
+    out = box_result(args)
+    if out is not None:
+        print(json.dumps(out))
+
+
+def box_result(args):
     """Box (3D) workloads: the DD cycle of the paper's 3D timing (every
     subdomain runs exactly 5 WaveHoltz iterations from random complex
     interface data, one launch) against one whole-box operator
-    evaluation."""
+    evaluation.  None after a --box-solve run (which prints its own line)."""
     import torch
     import workloads
     from paper_2606_21695_amd import wavedd as W
@@ -645,7 +651,8 @@ def box_bench(args):
     # the timed launches start from this random interface state
     W.dd3_sweep(h, g, None, 0.0, want_u=False)
     if args.box_solve:
-        return box_solve_bench(args, W, wl, h, X, Y, Z, s)
+        box_solve_bench(args, W, wl, h, X, Y, Z, s)
+        return None
     log(f"{args.config}: {s['n_sub']} subdomains of {s['n_local']} nodes, timing")
     ms, dof = W.dd3_time_sweep(h, args.steps, 5)
     n = s["n_global"]
@@ -692,7 +699,7 @@ def box_bench(args):
     if not args.no_cpu:
         log("cpu baseline (oracle WaveHoltz on sampled subdomains)")
         out["cpu_baseline"] = cpu_baseline3(wl)
-    print(json.dumps(out))
+    return out
 
 
 def box_solve_bench(args, W, wl, h, X, Y, Z, s):
@@ -734,6 +741,10 @@ def box_solve_bench(args, W, wl, h, X, Y, Z, s):
 
 
 def protocol_bench(args):
+    print(json.dumps(protocol_result(args)))
+
+
+def protocol_result(args):
     """The paper's DD-cycle timing (Sec. VII-A): sweeps of exactly 5
     WaveHoltz iterations per subdomain from random complex interface data,
     sources off, averaged over --steps launches after --warmup."""
@@ -800,7 +811,28 @@ def protocol_bench(args):
             out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                                "frac": gbs / 8000.0, "traffic": traffic, "alu_tflops": ach,
                                "kernel": kernel, "byte_per_dof_update": BYTES_STREAM[args.precision]}
-    print(json.dumps(out))
+    return out
+
+
+def other_workloads(args):
+    """The DD-cycle protocol (5 WaveHoltz iterations per subdomain, random
+    interface data) of the 512x512-element STREAM workload and the 64^3 box
+    workload in FP64, a few seconds each, beside the default line: value,
+    ms per DD cycle, roofline (a failure is recorded, not raised)."""
+    res = {}
+    for name, fn, cfg in (("c3_protocol_fp64", protocol_result, "c3"),
+                          ("c6_protocol_fp64", box_result, "c6")):
+        a = argparse.Namespace(**vars(args))
+        a.config, a.precision, a.steps, a.layout = cfg, "fp64", 3, "auto"
+        a.no_cpu, a.box_solve, a.protocol = True, False, True
+        try:
+            r = fn(a)
+            res[name] = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "config",
+                                           "roofline", "dd_cycle_over_operator") if k in r}
+        except Exception as ex:   # the default line stays valid without them
+            res[name] = {"error": repr(ex)}
+        log(f"{name} done")
+    return res
 
 
 def main():
@@ -820,6 +852,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c1", action="store_true",
                     help="skip the 16x16-element latency solves of the default run")
+    ap.add_argument("--no-protocols", action="store_true",
+                    help="skip the 512x512 and box DD-cycle lines of the default run")
     ap.add_argument("--global-lu", action="store_true",
                     help="also time the oracle's global sparse LU of the workload")
     ap.add_argument("--no-variants", action="store_true",
@@ -978,11 +1012,13 @@ def main():
         names = (args.variants.split(",") if args.variants else
                  ["fp32_refined_relaxed"] if args.config == "c3" else list(VARIANTS))
         out["variants"], sols = variants(W, wl, names, args.max_wh, args.progress,
-                                         steps=min(2, args.steps))
+                                         steps=min(5, args.steps))
     c1_sols = {}
     if args.config == "c2" and not args.no_c1:
         out["c1_latency"], c1_sols = c1_latency(W)
         log("c1 latency done")
+    if args.config == "c2" and not args.no_protocols:
+        out["other_workloads"] = other_workloads(args)
     if not args.no_cpu:
         # the oracle: DD with exact subdomain solves at the same outer
         # tolerance on the host's cores; every GPU solution is compared with it
