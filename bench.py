@@ -816,14 +816,16 @@ def protocol_result(args):
 
 def other_workloads(args):
     """The DD-cycle protocol (5 WaveHoltz iterations per subdomain, random
-    interface data) of the 512x512-element STREAM workload and the 64^3 box
-    workload in FP64, a few seconds each, beside the default line: value,
-    ms per DD cycle, roofline (a failure is recorded, not raised)."""
+    interface data) of the 512x512-element STREAM workload (FP64 and FP32)
+    and the 64^3 box workload (FP64), a few seconds each, beside the default
+    line: value, ms per DD cycle, roofline (a failure is recorded, not
+    raised)."""
     res = {}
-    for name, fn, cfg in (("c3_protocol_fp64", protocol_result, "c3"),
-                          ("c6_protocol_fp64", box_result, "c6")):
+    for name, fn, cfg, prec in (("c3_protocol_fp64", protocol_result, "c3", "fp64"),
+                                ("c3_protocol_fp32", protocol_result, "c3", "fp32"),
+                                ("c6_protocol_fp64", box_result, "c6", "fp64")):
         a = argparse.Namespace(**vars(args))
-        a.config, a.precision, a.steps, a.layout = cfg, "fp64", 3, "auto"
+        a.config, a.precision, a.steps, a.layout = cfg, prec, 3, "auto"
         a.no_cpu, a.box_solve, a.protocol = True, False, True
         try:
             r = fn(a)

@@ -98,6 +98,8 @@ def test_other_workloads_lines_through_a_stand_in_library():
     out = json.loads(r.stdout.strip().splitlines()[-1])
     c3, c6 = out["c3_protocol_fp64"], out["c6_protocol_fp64"]
     assert "error" not in c3 and "error" not in c6, out
+    assert "error" not in out["c3_protocol_fp32"], out
+    assert out["c3_protocol_fp32"]["roofline"]["byte_per_dof_update"] == 40
     assert c3["value"] == pytest.approx(1.6e9 / 20e-3)
     assert c3["config"]["kernel"] == "sweep_stream_coop_kernel"
     assert c3["roofline"]["bound"] == "hbm" and c3["roofline"]["unit"] == "GB/s"
